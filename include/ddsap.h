@@ -1,0 +1,179 @@
+/*
+ * ddsap.h -- C ABI of libddsap.so, an MI355X (gfx950) implementation of the
+ * Wilson-clover Dirac operator, the red-black Schwarz alternating procedure
+ * (SAP) built from block-local minimal-residual (MR) solves, and
+ * SAP-preconditioned flexible GMRES with an FP64 outer iteration.
+ *
+ * Paper: P. Georg, D. Richtmann, T. Wettig, "DD-alphaAMG on QPACE 3"
+ * (Lattice 2017).  Sec. 1 states the task (solve the discretised Dirac
+ * equation); Sec. 3.1 names the hot path (the MR inversion within a domain and
+ * the entire Schwarz method, Tables 1 and 2), mixed precision with some data
+ * structures held in half precision (Listing 1 rounds to nearest even), and
+ * Sec. 5 the solver's use as an external library that transforms the data
+ * layout at entry.  The operator itself follows Sheikholeslami & Wohlert (1985)
+ * in the mass form used by DD-alphaAMG:
+ *
+ *   (D psi)(x) = (4 + m0) psi(x) + C(x) psi(x)
+ *              - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                           + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *   C(x) = -(csw/32) sum_{mu,nu} g_mu g_nu (x) (Q_munu(x) - Q_numu(x))
+ *
+ * with Q the four-leaf clover, Euclidean chiral gamma matrices
+ * (g_5 = diag(1,1,-1,-1)), and the fermion boundary sign bcs[mu] on every hop
+ * that wraps around the lattice.  SAP follows Luescher, Comput. Phys. Commun.
+ * 156 (2004) 209; MR follows Saad's textbook (Sec. 5.3.2); FGMRES follows
+ * Saad, SIAM J. Sci. Comput. 14 (1993) 461.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every call
+ * ---------------------------------------------------------------------------
+ * Canonical (caller) layouts, complex numbers as interleaved (re, im) doubles:
+ *   site    s = x + Lx*(y + Ly*(z + Lz*t))
+ *   gauge   U[s][mu][a][b]            mu = x, y, z, t          (18 doubles/site/mu)
+ *   spinor  psi[rhs][s][spin][colour]                          (24 doubles/site)
+ *   clover  C[s][k][i][j]  k = chiral half (spins 0-1, spins 2-3),
+ *                          i, j = (spin - 2k)*3 + colour       (144 doubles/site)
+ * Blocked (device) layout: the library's own, reached through
+ * dd_pack_spinor / dd_unpack_spinor; dd_spinor_bytes gives its size.  The
+ * Schwarz blocks are 4x4x4x4 sites; the number of blocks per direction must be
+ * even or one (red-black colouring).  Block id (canonical) =
+ * bx + NBx*(by + NBy*(bz + NBz*bt)); its colour is (bx+by+bz+bt) mod 2.
+ *
+ * Precision (dd_prec): FP64, FP32, or FP16 storage with FP32 arithmetic.
+ * Conversions to lower precision round to nearest even.
+ *
+ * Ownership: the caller owns every pointer it passes.  Device pointers are
+ * HIP device allocations on the context's device (e.g. torch tensors'
+ * data_ptr()).  The context copies the gauge/clover fields it is given and
+ * owns all workspaces.  Calls enqueue on the context's stream and return
+ * without waiting unless stated; device faults surface at the next
+ * synchronising call.  One context serves one host thread at a time.
+ *
+ * Errors: every call returns a dd_status.  The library never aborts, never
+ * throws across this boundary and never prints; dd_last_error gives the
+ * message of the last failure on a context (or of the last failed dd_create
+ * when passed NULL).
+ */
+#ifndef DDSAP_H
+#define DDSAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_ABI_VERSION 1
+#define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
+
+typedef enum {
+    DD_OK = 0,
+    DD_INVALID_ARG = 1,   /* bad size, pointer, blocking, precision or parameter */
+    DD_OOM = 2,           /* a device allocation failed                           */
+    DD_HIP_ERROR = 3,     /* a HIP runtime call failed                            */
+    DD_NOT_CONVERGED = 4, /* max restarts reached; x holds the best iterate       */
+    DD_BREAKDOWN = 5,     /* Arnoldi breakdown without convergence                */
+    DD_NAN = 6,           /* NaN or Inf found in an input or a residual           */
+    DD_NO_FIELD = 7       /* the call needs a gauge field that was never set      */
+} dd_status;
+
+typedef enum { DD_F64 = 0, DD_F32 = 1, DD_F16 = 2 } dd_prec;
+
+typedef struct dd_ctx dd_ctx;
+
+/* Parameters of dd_solve (FGMRES(m) preconditioned by ncy SAP cycles of nmr
+ * MR steps per block, in precision sap_prec; the outer iteration is FP64). */
+typedef struct {
+    int m;            /* Krylov dimension per restart cycle, 1..32 (20)         */
+    double tol;       /* stop when ||b - D x||_2 / ||b||_2 <= tol (1e-10)       */
+    int max_restarts; /* restart cycles before DD_NOT_CONVERGED (100)            */
+    int ncy;          /* SAP cycles per preconditioner call; 0 = no precond (4) */
+    int nmr;          /* MR steps per block and sweep (4)                        */
+    int sap_prec;     /* dd_prec of the smoother (DD_F32)                        */
+} dd_params;
+
+/* Per right-hand-side result of dd_solve. */
+typedef struct {
+    int status;          /* dd_status of this right-hand side                   */
+    int iterations;      /* Arnoldi steps taken                                 */
+    int restarts;        /* restart cycles started                              */
+    int sap_calls;       /* preconditioner applications                         */
+    double rel_residual; /* final true residual ||b - D x|| / ||b|| (FP64, GPU) */
+} dd_solve_info;
+
+/* ABI version of the loaded library (DD_ABI_VERSION). */
+int dd_abi_version(void);
+
+/* Fill *p with the defaults shown above. */
+void dd_default_params(dd_params *p);
+
+/* Create a context for a Lx x Ly x Lz x Lt lattice on the current HIP device.
+ *   dims   lattice extents; each a multiple of 4 (the Schwarz block extent);
+ *   bcs    fermion boundary sign per direction, +1 or -1 (e.g. {1,1,1,-1});
+ *   stream hipStream_t to enqueue on (NULL = the null stream);
+ *   out    receives the context.
+ * DD_INVALID_ARG if an extent is not a positive multiple of 4 or a direction
+ * has an odd number (>1) of blocks; DD_OOM / DD_HIP_ERROR on device failure. */
+dd_status dd_create(const int dims[4], const int bcs[4], void *stream, dd_ctx **out);
+
+/* Release the context and every device buffer it owns (synchronises). */
+dd_status dd_destroy(dd_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last dd_create if NULL). */
+const char *dd_last_error(const dd_ctx *ctx);
+
+/* Wait for all work enqueued on the context's stream. */
+dd_status dd_synchronize(dd_ctx *ctx);
+
+/* Setup (not timed): copy the canonical FP64 gauge field U (host pointer,
+ * 72*V doubles), build the clover term with coefficient csw on the device in
+ * FP64, and store links and clover in the blocked layout in FP64, FP32 and
+ * FP16.  Synchronises.  DD_NAN if U holds NaN/Inf. */
+dd_status dd_set_gauge(dd_ctx *ctx, const double *U_host, double csw);
+
+/* Replace the clover term by an explicit one (host pointer, canonical clover
+ * layout, 144*V doubles; each 6x6 half must be Hermitian, only its upper
+ * triangle and real diagonal are read).  Requires dd_set_gauge first. */
+dd_status dd_set_clover(dd_ctx *ctx, const double *C_host);
+
+/* Bytes of one blocked spinor buffer holding nrhs right-hand sides. */
+size_t dd_spinor_bytes(const dd_ctx *ctx, int prec, int nrhs);
+
+/* Layout transform: canonical FP64 spinors (device pointer, nrhs*24*V
+ * doubles) -> blocked buffer of precision prec (device pointer), and back.
+ * Down-conversion rounds to nearest even; no scaling is applied. */
+dd_status dd_pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs);
+dd_status dd_unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs);
+
+/* y = D x for nrhs right-hand sides, right-hand side r with mass m0[r]
+ * (host array of nrhs doubles).  x, y: blocked device buffers of precision
+ * prec; they must not overlap. */
+dd_status dd_apply_D(dd_ctx *ctx, const double *m0, const void *x, void *y, int prec, int nrhs);
+
+/* y_B = D_BB x_B on one Schwarz block (canonical block id): D restricted to
+ * the block, every hop that leaves the block dropped.  x, y: whole-lattice
+ * blocked buffers (one right-hand side); only block block_id of x is read
+ * and only block block_id of y is written. */
+dd_status dd_apply_D_block(dd_ctx *ctx, double m0, long block_id, const void *x, void *y, int prec);
+
+/* psi = SAP(eta): ncy cycles of red-black block sweeps from psi = 0; each
+ * sweep forms the block residual eta_B - (D psi)_B and adds nmr MR steps on
+ * D_BB to psi_B (colour 0 first).  eta, psi: blocked device buffers of
+ * precision prec (nrhs right-hand sides, masses m0[r]); psi is overwritten. */
+dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr,
+                 int prec, int nrhs);
+
+/* Solve D x_r = b_r (r < nrhs) with FGMRES(m) preconditioned by SAP in
+ * params->sap_prec, the Arnoldi basis, orthogonalisation, true residuals and
+ * reductions in FP64 on the device.  b, x: canonical FP64 spinors (device
+ * pointers, nrhs*24*V doubles); x holds the initial guess on entry (zero it
+ * for x0 = 0) and the solution on exit.  m0: host array of nrhs masses.
+ * info (host, may be NULL): nrhs entries.  Synchronises.  Returns DD_OK if
+ * every right-hand side converged, else the first failing status. */
+dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs,
+                   const dd_params *params, dd_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,301 @@
+// C ABI of libddsap (declarations and contracts in include/ddsap.h).  Every
+// entry point validates its arguments, converts internal failures into a
+// dd_status plus a message, and never lets a C++ exception cross the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+size_t real_bytes(int prec) { return prec == DD_F64 ? 8 : prec == DD_F32 ? 4 : 2; }
+
+size_t spinor_bytes(const GeomHost &g, int prec, int nrhs)
+{
+    return (size_t)g.V * 12 * 2 * real_bytes(prec) * (size_t)nrhs;
+}
+
+} // namespace dd
+
+namespace {
+
+thread_local std::string g_create_error;
+
+dd_status fail(dd_ctx *ctx, const dd::Status &s)
+{
+    if (ctx) ctx->err = s.msg;
+    return s.code;
+}
+
+dd_status fail(dd_ctx *ctx, dd_status code, const std::string &msg) { return fail(ctx, dd::Status{code, msg}); }
+
+bool prec_ok(int p) { return p == DD_F64 || p == DD_F32 || p == DD_F16; }
+
+template <typename F> dd_status guarded(dd_ctx *ctx, F &&f)
+{
+    try {
+        dd::Status s = f();
+        if (!s.good()) return fail(ctx, s);
+        return DD_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DD_OOM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DD_HIP_ERROR, "unexpected internal error");
+    }
+}
+
+dd::Status set_device(dd_ctx *ctx)
+{
+    DD_HIP_TRY(hipSetDevice(ctx->device));
+    return dd::Status::ok();
+}
+
+} // namespace
+
+extern "C" {
+
+int dd_abi_version(void) { return DD_ABI_VERSION; }
+
+void dd_default_params(dd_params *p)
+{
+    if (!p) return;
+    p->m = 20;
+    p->tol = 1e-10;
+    p->max_restarts = 100;
+    p->ncy = 4;
+    p->nmr = 4;
+    p->sap_prec = DD_F32;
+}
+
+const char *dd_last_error(const dd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+dd_status dd_create(const int dims[4], const int bcs[4], void *stream, dd_ctx **out)
+{
+    g_create_error.clear();
+    if (!dims || !bcs || !out) {
+        g_create_error = "dd_create: null argument";
+        return DD_INVALID_ARG;
+    }
+    *out = nullptr;
+    dd::GeomHost g{};
+    long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (dims[mu] < 4 || dims[mu] % 4 != 0) {
+            g_create_error = "dd_create: every extent must be a positive multiple of the block extent 4";
+            return DD_INVALID_ARG;
+        }
+        int nb = dims[mu] / 4;
+        if (nb != 1 && nb % 2 != 0) {
+            g_create_error = "dd_create: the number of blocks per direction must be even or one";
+            return DD_INVALID_ARG;
+        }
+        if (bcs[mu] != 1 && bcs[mu] != -1) {
+            g_create_error = "dd_create: boundary signs must be +1 or -1";
+            return DD_INVALID_ARG;
+        }
+        g.L[mu] = dims[mu];
+        g.nb[mu] = nb;
+        g.bcs[mu] = bcs[mu];
+        V *= dims[mu];
+    }
+    if (V > (1L << 28)) {
+        g_create_error = "dd_create: lattice too large";
+        return DD_INVALID_ARG;
+    }
+    g.V = V;
+    g.nblocks = (int)(V / dd::BS_HOST);
+    g.bstride[0] = 1;
+    for (int mu = 1; mu < 4; ++mu) g.bstride[mu] = g.bstride[mu - 1] * g.nb[mu - 1];
+    dd_ctx *ctx = nullptr;
+    try {
+        ctx = new dd_ctx();
+    } catch (...) {
+        g_create_error = "dd_create: host allocation failed";
+        return DD_OOM;
+    }
+    ctx->g = g;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        g_create_error = "dd_create: no HIP device";
+        delete ctx;
+        return DD_HIP_ERROR;
+    }
+    // colour lists in canonical block order: the sweep kernels map contiguous
+    // ranges of these lists onto one XCD each
+    std::vector<int> lists[2];
+    for (int b = 0; b < g.nblocks; ++b) {
+        int t = b, sum = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            sum += t % g.nb[mu];
+            t /= g.nb[mu];
+        }
+        lists[sum & 1].push_back(b);
+    }
+    for (int c = 0; c < 2; ++c) {
+        ctx->ncolour[c] = (int)lists[c].size();
+        if (lists[c].empty()) continue;
+        dd::Status s = ctx->colour_blocks[c].alloc(lists[c].size() * sizeof(int));
+        if (s.good() && hipMemcpy(ctx->colour_blocks[c].p, lists[c].data(), lists[c].size() * sizeof(int),
+                                  hipMemcpyHostToDevice) != hipSuccess)
+            s = dd::Status{DD_HIP_ERROR, "copy of the colour lists failed"};
+        if (!s.good()) {
+            g_create_error = "dd_create: " + s.msg;
+            delete ctx;
+            return s.code;
+        }
+    }
+    *out = ctx;
+    return DD_OK;
+}
+
+dd_status dd_destroy(dd_ctx *ctx)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return DD_OK;
+}
+
+dd_status dd_synchronize(dd_ctx *ctx)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return dd::Status::ok();
+    });
+}
+
+dd_status dd_set_gauge(dd_ctx *ctx, const double *U_host, double csw)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!U_host || !std::isfinite(csw)) return fail(ctx, DD_INVALID_ARG, "dd_set_gauge: null field or bad csw");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        size_t n = (size_t)ctx->g.V * 72;
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(U_host[i])) return dd::Status{DD_NAN, "dd_set_gauge: gauge field holds NaN or Inf"};
+        dd::DevBuf U;
+        DD_TRY(U.alloc(n * sizeof(double)));
+        DD_HIP_TRY(hipMemcpyAsync(U.p, U_host, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        DD_TRY(dd::build_fields(ctx, U.as<double>(), csw));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->has_field = true;
+        ctx->csw = csw;
+        return dd::Status::ok();
+    });
+}
+
+dd_status dd_set_clover(dd_ctx *ctx, const double *C_host)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!C_host) return fail(ctx, DD_INVALID_ARG, "dd_set_clover: null clover");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_set_clover: call dd_set_gauge first");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        size_t n = (size_t)ctx->g.V * 144;
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(C_host[i])) return dd::Status{DD_NAN, "dd_set_clover: clover holds NaN or Inf"};
+        dd::DevBuf C;
+        DD_TRY(C.alloc(n * sizeof(double)));
+        DD_HIP_TRY(hipMemcpyAsync(C.p, C_host, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        DD_TRY(dd::set_clover_canon(ctx, C.as<double>()));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return dd::Status::ok();
+    });
+}
+
+size_t dd_spinor_bytes(const dd_ctx *ctx, int prec, int nrhs)
+{
+    if (!ctx || !prec_ok(prec) || nrhs < 1) return 0;
+    return dd::spinor_bytes(ctx->g, prec, nrhs);
+}
+
+dd_status dd_pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!canon || !blocked || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS)
+        return fail(ctx, DD_INVALID_ARG, "dd_pack_spinor: bad argument");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::pack_spinor(ctx, canon, blocked, prec, nrhs);
+    });
+}
+
+dd_status dd_unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!canon || !blocked || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS)
+        return fail(ctx, DD_INVALID_ARG, "dd_unpack_spinor: bad argument");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::unpack_spinor(ctx, blocked, canon, prec, nrhs);
+    });
+}
+
+dd_status dd_apply_D(dd_ctx *ctx, const double *m0, const void *x, void *y, int prec, int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!m0 || !x || !y || x == y || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS)
+        return fail(ctx, DD_INVALID_ARG, "dd_apply_D: bad argument");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_apply_D: no gauge field");
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_apply_D: non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::launch_dslash(ctx, m0, nrhs, x, prec, y, prec, prec, nullptr);
+    });
+}
+
+dd_status dd_apply_D_block(dd_ctx *ctx, double m0, long block_id, const void *x, void *y, int prec)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!x || !y || x == y || !prec_ok(prec) || !std::isfinite(m0))
+        return fail(ctx, DD_INVALID_ARG, "dd_apply_D_block: bad argument");
+    if (block_id < 0 || block_id >= ctx->g.nblocks) return fail(ctx, DD_INVALID_ARG, "dd_apply_D_block: bad block id");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_apply_D_block: no gauge field");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::launch_dslash_block(ctx, m0, (int)block_id, x, y, prec);
+    });
+}
+
+dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr, int prec, int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!m0 || !eta || !psi || eta == psi || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS || ncy < 0 || nmr < 0)
+        return fail(ctx, DD_INVALID_ARG, "dd_sap: bad argument");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_sap: no gauge field");
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap: non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec);
+    });
+}
+
+dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params *params,
+                   dd_solve_info *info)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    dd_params p;
+    dd_default_params(&p);
+    if (params) p = *params;
+    if (!m0 || !b || !x || (const void *)b == (const void *)x || nrhs < 1 || nrhs > DD_MAX_RHS)
+        return fail(ctx, DD_INVALID_ARG, "dd_solve: bad argument");
+    if (p.m < 1 || p.m > 32 || !(p.tol > 0) || p.max_restarts < 0 || p.ncy < 0 || p.nmr < 0 || !prec_ok(p.sap_prec))
+        return fail(ctx, DD_INVALID_ARG, "dd_solve: bad parameters (1 <= m <= 32, tol > 0, ...)");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_solve: no gauge field");
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_solve: non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::solve(ctx, m0, b, x, nrhs, p, info);
+    });
+}
+
+} // extern "C"

@@ -1,0 +1,121 @@
+// Host-side internals of libddsap: the context, launch wrappers of the HIP
+// kernels and error plumbing.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ddsap.h"
+
+namespace dd {
+
+constexpr int BS_HOST = 256; // sites per 4^4 Schwarz block
+
+struct Status {
+    dd_status code = DD_OK;
+    std::string msg;
+    static Status ok() { return {}; }
+    bool good() const { return code == DD_OK; }
+};
+
+#define DD_HIP_TRY(expr)                                                                               \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return dd::Status{e_ == hipErrorOutOfMemory ? DD_OOM : DD_HIP_ERROR,                        \
+                              std::string(#expr) + ": " + hipGetErrorString(e_)};                      \
+    } while (0)
+
+#define DD_TRY(expr)                                                                                   \
+    do {                                                                                               \
+        dd::Status s_ = (expr);                                                                        \
+        if (!s_.good()) return s_;                                                                     \
+    } while (0)
+
+// Owned device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    Status alloc(size_t n)
+    {
+        if (n == bytes && p) return Status::ok();
+        release();
+        if (n == 0) return Status::ok();
+        DD_HIP_TRY(hipMalloc(&p, n));
+        bytes = n;
+        return Status::ok();
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct GeomHost {
+    int L[4];
+    int nb[4];
+    int bstride[4];
+    int nblocks;
+    long V;
+    int bcs[4];
+};
+
+struct SolverWork; // solver.hip
+struct SolverWorkDeleter {
+    void operator()(SolverWork *w) const; // solver.hip
+};
+
+} // namespace dd
+
+struct dd_ctx {
+    dd::GeomHost g{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool has_field = false;
+    double csw = 0;
+    dd::DevBuf links[3];  // blocked links per dd_prec
+    dd::DevBuf clover[3]; // blocked clover per dd_prec
+    dd::DevBuf colour_blocks[2]; // int block ids of each colour, XCD-friendly order
+    int ncolour[2] = {0, 0};
+    std::string err;
+    std::unique_ptr<dd::SolverWork, dd::SolverWorkDeleter> work;
+};
+
+namespace dd {
+
+size_t real_bytes(int prec); // 8, 4, 2
+size_t spinor_bytes(const GeomHost &g, int prec, int nrhs);
+
+// fields.hip
+Status build_fields(dd_ctx *ctx, const double *U_dev_canon, double csw);
+Status set_clover_canon(dd_ctx *ctx, const double *C_dev_canon);
+Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs);
+Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs);
+Status any_nonfinite(dd_ctx *ctx, const double *p, size_t n, bool &bad);
+
+// dslash.hip
+// out = D in (resid == nullptr) or out = resid - D in.  in_prec may differ
+// from out_prec only for (F32 in, F64 out) and (F64 in, F64 out).
+Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
+                     int field_prec, const double *resid);
+Status launch_dslash_block(dd_ctx *ctx, double m0, int block_id, const void *in, void *out, int prec);
+
+// sap.hip
+Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec);
+
+// solver.hip
+Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,
+             dd_solve_info *info);
+void free_solver_work(dd_ctx *ctx);
+
+} // namespace dd

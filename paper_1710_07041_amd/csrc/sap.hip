@@ -1,0 +1,276 @@
+// Red-black Schwarz alternating procedure (SAP) with block-local minimal
+// residual (MR) solves -- the "MR inversion within a domain" and the "entire
+// Schwarz method" whose per-core rates the paper reports (Sec. 3.1, Tables 1
+// and 2); the algorithm is Luescher's multiplicative SAP (Comput. Phys.
+// Commun. 156 (2004) 209) with Saad's MR iteration on each block.
+//
+// One launch sweeps every block of one colour.  One 256-thread workgroup owns
+// one 4^4 block, one thread one site, and keeps everything the MR loop needs
+// on chip:
+//   * the site's four forward links (and, below FP64, its clover term) live
+//     in registers for the whole sweep and every right-hand side;
+//   * D_BB is applied direction by direction: each thread publishes the
+//     spin-projected half spinor of its site for the +mu hop of site x-mu and
+//     U_mu(x)^+ times the projected half spinor for the -mu hop of site x+mu
+//     through LDS, so no spinor leaves the chip inside the MR loop;
+//   * the two block dot products per MR step reduce with wavefront shuffles
+//     and a fixed-order combine of the four wavefronts (deterministic).
+// The block residual eta_B - (D psi)_B is formed on entry: the in-block part
+// by the same LDS exchange, the hops that leave the block by reading the
+// other colour's psi (and, for -mu hops, the neighbour's link) from memory.
+// Blocks of one colour share no site and read only the other colour's psi,
+// so a sweep needs no synchronisation between workgroups.
+#include "dd_device.h"
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+
+struct SArgs {
+    Geom g;
+    const int *blocks; // block ids of the swept colour
+    int nblk;
+    int nrhs;
+    int nmr;
+    int mode; // 0: psi = 0 everywhere; 1: psi_B = 0 on this colour; 2: general
+    double m0[MAXRHS];
+};
+
+template <typename A> struct Lds {
+    cx<A> hf[6][BS]; // projected half spinors for +mu hops
+    cx<A> hb[6][BS]; // U^+ times projected half spinors for -mu hops
+    A red[4][4];
+};
+
+template <int MU, typename A>
+__device__ __forceinline__ void exchange_hop(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
+                                             const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
+{
+    cx<A> h[6], t[6];
+    proj_minus<MU>(v, h);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.hf[c][s] = h[c];
+    proj_plus<MU>(v, h);
+    su3_mul_adj(U, h, t);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.hb[c][s] = t[c];
+    __syncthreads();
+    int bn, sn, sign;
+    bool inb;
+    neighbour<MU, +1>(g, b, bc, s, bn, sn, sign, inb);
+    if (inb) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
+        su3_mul(U, h, t);
+        recon_minus<MU>(q, t, (A)(-0.5 * sign));
+    }
+    neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
+    if (inb) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
+        recon_plus<MU>(q, t, (A)(-0.5 * sign));
+    }
+    __syncthreads();
+}
+
+// q = D_BB v on the block (all threads of the workgroup take part)
+template <typename S, typename A, bool REGCLOV>
+__device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
+                                            const cx<A> U[4][9], const cx<A> cl[36],
+                                            const vec2_t<S> *__restrict__ clov_g, A diag, const cx<A> v[12],
+                                            cx<A> q[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+    if (REGCLOV) {
+        clover_mac(cl, diag, v, q);
+    } else {
+        cx<A> c2[36];
+        const vec2_t<S> *cp = clov_g + (long)b * 36 * BS + s;
+#pragma unroll
+        for (int e = 0; e < 36; ++e) c2[e] = ldc<A>(cp + e * BS);
+        clover_mac(c2, diag, v, q);
+    }
+    exchange_hop<0>(L, g, b, bc, s, U[0], v, q);
+    exchange_hop<1>(L, g, b, bc, s, U[1], v, q);
+    exchange_hop<2>(L, g, b, bc, s, U[2], v, q);
+    exchange_hop<3>(L, g, b, bc, s, U[3], v, q);
+}
+
+// hops of site s whose neighbour lies outside the block: read psi (and the
+// neighbour's link for -mu hops) from memory and accumulate into q
+template <int MU, typename S, typename A>
+__device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
+                                          const vec2_t<S> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
+                                          const cx<A> U[9], cx<A> q[12])
+{
+    int bn, sn, sign;
+    bool inb;
+    cx<A> p[12], h[6], t[6];
+    neighbour<MU, +1>(g, b, bc, s, bn, sn, sign, inb);
+    if (!inb) {
+        const vec2_t<S> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
+        proj_minus<MU>(p, h);
+        su3_mul(U, h, t);
+        recon_minus<MU>(q, t, (A)(-0.5 * sign));
+    }
+    neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
+    if (!inb) {
+        const vec2_t<S> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
+        cx<A> Un[9];
+        const vec2_t<S> *u = links + ((long)bn * 4 + MU) * 9 * BS + sn;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Un[e] = ldc<A>(u + e * BS);
+        proj_plus<MU>(p, h);
+        su3_mul_adj(Un, h, t);
+        recon_plus<MU>(q, t, (A)(-0.5 * sign));
+    }
+}
+
+template <typename A> __device__ __forceinline__ A wave_sum(A v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename S, typename A, bool REGCLOV>
+__global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ eta, vec2_t<S> *__restrict__ psi,
+                                                  const vec2_t<S> *__restrict__ links,
+                                                  const vec2_t<S> *__restrict__ clov, SArgs a)
+{
+    __shared__ Lds<A> L;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = a.blocks[i];
+    const int s = threadIdx.x;
+    const int lane = s & 63, wave = s >> 6;
+    int bc[4];
+    block_coords(a.g, b, bc);
+
+    cx<A> U[4][9];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[mu][e] = ldc<A>(u + e * BS);
+    }
+    cx<A> cl[REGCLOV ? 36 : 1];
+    if (REGCLOV) {
+        const vec2_t<S> *cp = clov + (long)b * 36 * BS + s;
+#pragma unroll
+        for (int e = 0; e < (REGCLOV ? 36 : 1); ++e) cl[e] = ldc<A>(cp + e * BS);
+    }
+
+    for (int r = 0; r < a.nrhs; ++r) {
+        const A diag = (A)(4.0 + a.m0[r]);
+        const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
+        cx<A> rr[12], del[12], q[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(eta + sp + c * BS);
+        if (a.mode == 2) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) del[c] = ldc<A>(psi + sp + c * BS);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) del[c] = mk<A>(0, 0);
+        }
+        if (a.mode != 0) {
+            // rho = eta - (D psi)_B ; psi_B is held in del
+            if (a.mode == 2) {
+                block_apply<S, A, REGCLOV>(L, a.g, b, bc, s, U, cl, clov, diag, del, q);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+            }
+            face_hops<0, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[0], q);
+            face_hops<1, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[1], q);
+            face_hops<2, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[2], q);
+            face_hops<3, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[3], q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = rr[c] - q[c];
+        }
+        // MR on D_BB: del accumulates alpha * r on top of psi_B
+        for (int it = 0; it < a.nmr; ++it) {
+            block_apply<S, A, REGCLOV>(L, a.g, b, bc, s, U, cl, clov, diag, rr, q);
+            A qr_re = 0, qr_im = 0, qq = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                qr_re = fma(q[c].re, rr[c].re, qr_re);
+                qr_re = fma(q[c].im, rr[c].im, qr_re);
+                qr_im = fma(q[c].re, rr[c].im, qr_im);
+                qr_im = fma(-q[c].im, rr[c].re, qr_im);
+                qq = fma(q[c].re, q[c].re, qq);
+                qq = fma(q[c].im, q[c].im, qq);
+            }
+            qr_re = wave_sum(qr_re);
+            qr_im = wave_sum(qr_im);
+            qq = wave_sum(qq);
+            if (lane == 0) {
+                L.red[wave][0] = qr_re;
+                L.red[wave][1] = qr_im;
+                L.red[wave][2] = qq;
+            }
+            __syncthreads();
+            qr_re = ((L.red[0][0] + L.red[1][0]) + L.red[2][0]) + L.red[3][0];
+            qr_im = ((L.red[0][1] + L.red[1][1]) + L.red[2][1]) + L.red[3][1];
+            qq = ((L.red[0][2] + L.red[1][2]) + L.red[2][2]) + L.red[3][2];
+            if (qq == (A)0) break; // uniform across the workgroup
+            const cx<A> alpha = mk<A>(qr_re / qq, qr_im / qq);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                cmac(del[c], alpha, rr[c]);
+                rr[c] = rr[c] - alpha * q[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, del[c]);
+    }
+}
+
+template <typename S, typename A, bool REGCLOV>
+Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
+{
+    k_sap_sweep<S, A, REGCLOV><<<a.nblk, BS, 0, ctx->stream>>>(
+        static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
+        static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p), a);
+    DD_HIP_TRY(hipGetLastError());
+    return Status::ok();
+}
+
+} // namespace
+
+Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec)
+{
+    if (ncy == 0) {
+        DD_HIP_TRY(hipMemsetAsync(psi, 0, spinor_bytes(ctx->g, prec, nrhs), ctx->stream));
+        return Status::ok();
+    }
+    SArgs a{};
+    for (int k = 0; k < 4; ++k) {
+        a.g.nb[k] = ctx->g.nb[k];
+        a.g.bstride[k] = ctx->g.bstride[k];
+        a.g.bcs[k] = ctx->g.bcs[k];
+    }
+    a.g.nblocks = ctx->g.nblocks;
+    a.nrhs = nrhs;
+    a.nmr = nmr;
+    for (int r = 0; r < nrhs; ++r) a.m0[r] = m0[r];
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int col = 0; col < 2; ++col) {
+            if (ctx->ncolour[col] == 0) continue;
+            a.blocks = ctx->colour_blocks[col].as<int>();
+            a.nblk = ctx->ncolour[col];
+            a.mode = (cy == 0 && col == 0) ? 0 : (cy == 0 ? 1 : 2);
+            if (prec == DD_F64) DD_TRY((sweep<double, double, false>(ctx, a, prec, eta, psi)));
+            else if (prec == DD_F32) DD_TRY((sweep<float, float, true>(ctx, a, prec, eta, psi)));
+            else DD_TRY((sweep<__half, float, true>(ctx, a, prec, eta, psi)));
+        }
+    return Status::ok();
+}
+
+} // namespace dd

@@ -1,0 +1,191 @@
+"""Thin ctypes binding of libddsap.so (C ABI declared in include/ddsap.h).
+
+Argument marshalling only: every step of the operator, the Schwarz smoother
+and the solver runs in the library's HIP kernels.  Device buffers are torch
+tensors on the GPU (PyTorch serves only for device memory and streams).  If the
+shared library is missing this module raises ImportError: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = Path(os.environ.get("DDSAP_LIB", _PKG / "libddsap.so"))
+
+if not LIB_PATH.exists():
+    raise ImportError(f"libddsap.so not found at {LIB_PATH}; build it with paper_1710_07041_amd/build.py "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(str(LIB_PATH))
+
+DD_OK, DD_INVALID_ARG, DD_OOM, DD_HIP_ERROR, DD_NOT_CONVERGED, DD_BREAKDOWN, DD_NAN, DD_NO_FIELD = range(8)
+STATUS_NAMES = ["DD_OK", "DD_INVALID_ARG", "DD_OOM", "DD_HIP_ERROR", "DD_NOT_CONVERGED", "DD_BREAKDOWN", "DD_NAN",
+                "DD_NO_FIELD"]
+DD_F64, DD_F32, DD_F16 = 0, 1, 2
+PREC = {"f64": DD_F64, "f32": DD_F32, "f16": DD_F16}
+DD_MAX_RHS = 16
+
+EXPORTS = [
+    "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
+    "dd_set_gauge", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
+    "dd_apply_D_block", "dd_sap", "dd_solve",
+]
+
+
+class dd_params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
+                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int)]
+
+
+class dd_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("sap_calls", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+_vp, _ip, _d, _i, _l, _sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int, \
+    ctypes.c_long, ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+_sigs = {
+    "dd_abi_version": ([], _i),
+    "dd_default_params": ([ctypes.POINTER(dd_params)], None),
+    "dd_create": ([_ip, _ip, _vp, ctypes.POINTER(_vp)], _i),
+    "dd_destroy": ([_vp], _i),
+    "dd_last_error": ([_vp], ctypes.c_char_p),
+    "dd_synchronize": ([_vp], _i),
+    "dd_set_gauge": ([_vp, _vp, _d], _i),
+    "dd_set_clover": ([_vp, _vp], _i),
+    "dd_spinor_bytes": ([_vp, _i, _i], _sz),
+    "dd_pack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
+    "dd_unpack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
+    "dd_apply_D": ([_vp, _dp, _vp, _vp, _i, _i], _i),
+    "dd_apply_D_block": ([_vp, _d, _l, _vp, _vp, _i], _i),
+    "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
+    "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class DDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+def abi_version() -> int:
+    return _lib.dd_abi_version()
+
+
+def default_params() -> dd_params:
+    p = dd_params()
+    _lib.dd_default_params(ctypes.byref(p))
+    return p
+
+
+def _ptr(t) -> int:
+    """Device or host address of a torch tensor / numpy array."""
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def _masses(m0, nrhs):
+    a = np.broadcast_to(np.asarray(m0, dtype=np.float64), (nrhs,)).copy()
+    return a, a.ctypes.data_as(_dp)
+
+
+class Context:
+    """One lattice on the current HIP device (wraps dd_ctx)."""
+
+    def __init__(self, dims, bcs=(1, 1, 1, -1), stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        self.volume = int(np.prod(self.dims))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._h = _vp()
+        st = _lib.dd_create((ctypes.c_int * 4)(*self.dims), (ctypes.c_int * 4)(*bcs), _vp(stream),
+                            ctypes.byref(self._h))
+        if st != DD_OK:
+            raise DDError(st, _lib.dd_last_error(None).decode())
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, st):
+        if st != DD_OK:
+            raise DDError(st, _lib.dd_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if self._h:
+            _lib.dd_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        self._check(_lib.dd_synchronize(self._h))
+
+    # -- C ABI, one method per entry point ------------------------------------
+    def set_gauge(self, U, csw):
+        """U: host complex128 array (V, 4, 3, 3) in canonical order."""
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        if U.size != self.volume * 36:
+            raise ValueError("gauge field has the wrong size")
+        self._check(_lib.dd_set_gauge(self._h, _vp(U.ctypes.data), float(csw)))
+
+    def set_clover(self, C):
+        """C: host complex128 array (V, 2, 6, 6): the two chiral 6x6 halves."""
+        C = np.ascontiguousarray(C, dtype=np.complex128)
+        if C.size != self.volume * 72:
+            raise ValueError("clover field has the wrong size")
+        self._check(_lib.dd_set_clover(self._h, _vp(C.ctypes.data)))
+
+    def spinor_bytes(self, prec, nrhs=1) -> int:
+        return int(_lib.dd_spinor_bytes(self._h, PREC.get(prec, prec), int(nrhs)))
+
+    def empty_blocked(self, prec, nrhs=1):
+        import torch
+        return torch.empty(self.spinor_bytes(prec, nrhs), dtype=torch.uint8, device="cuda")
+
+    def pack(self, canon, blocked, prec, nrhs=1):
+        self._check(_lib.dd_pack_spinor(self._h, _vp(_ptr(canon)), _vp(_ptr(blocked)), PREC.get(prec, prec),
+                                        int(nrhs)))
+
+    def unpack(self, blocked, canon, prec, nrhs=1):
+        self._check(_lib.dd_unpack_spinor(self._h, _vp(_ptr(blocked)), _vp(_ptr(canon)), PREC.get(prec, prec),
+                                          int(nrhs)))
+
+    def apply_D(self, m0, x, y, prec, nrhs=1):
+        _, mp = _masses(m0, nrhs)
+        self._check(_lib.dd_apply_D(self._h, mp, _vp(_ptr(x)), _vp(_ptr(y)), PREC.get(prec, prec), int(nrhs)))
+
+    def apply_D_block(self, m0, block_id, x, y, prec):
+        self._check(_lib.dd_apply_D_block(self._h, float(m0), int(block_id), _vp(_ptr(x)), _vp(_ptr(y)),
+                                          PREC.get(prec, prec)))
+
+    def sap(self, m0, eta, psi, ncy, nmr, prec, nrhs=1):
+        _, mp = _masses(m0, nrhs)
+        self._check(_lib.dd_sap(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), int(ncy), int(nmr),
+                                PREC.get(prec, prec), int(nrhs)))
+
+    def solve(self, m0, b, x, nrhs=1, params: dd_params | None = None, raise_on_fail=True):
+        """b, x: canonical complex128 device tensors (nrhs, V, 4, 3); x holds x0."""
+        _, mp = _masses(m0, nrhs)
+        infos = (dd_solve_info * nrhs)()
+        p = params if params is not None else default_params()
+        st = _lib.dd_solve(self._h, mp, _vp(_ptr(b)), _vp(_ptr(x)), int(nrhs), ctypes.byref(p), infos)
+        out = [{k: getattr(i, k) for k, _ in dd_solve_info._fields_} for i in infos]
+        if raise_on_fail and st not in (DD_OK,):
+            raise DDError(st, _lib.dd_last_error(self._h).decode())
+        return st, out

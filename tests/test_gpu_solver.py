@@ -1,0 +1,149 @@
+"""GPU parity of the Schwarz smoother and of SAP-FGMRES solves, through the C ABI.
+
+SAP is an iteration, so the GPU result is compared with the oracle's SAP at a
+precision-dependent tolerance; a solve is correct when the oracle's own FP64
+operator gives relative residual <= 1e-10 for the GPU solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import BC, REL_TOL_SAP, Lattice, rel, to_dev, to_host
+from paper_1710_07041_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_sap(lat, eta, m0, ncy, nmr, prec, nrhs=None):
+    import torch
+    n = 1 if nrhs is None else nrhs
+    x = to_dev(eta)
+    eb = lat.ctx.empty_blocked(prec, n)
+    pb = lat.ctx.empty_blocked(prec, n)
+    lat.ctx.pack(x, eb, prec, n)
+    lat.ctx.sap(m0, eb, pb, ncy, nmr, prec, n)
+    y = torch.empty_like(x)
+    lat.ctx.unpack(pb, y, prec, n)
+    lat.ctx.synchronize()
+    return to_host(y)
+
+
+@pytest.fixture(scope="module", params=[(8, 8, 8, 8), (4, 4, 8, 24), (4, 4, 4, 4)], ids=lambda d: "x".join(map(str, d)))
+def lat(request):
+    return Lattice(request.param, eps=0.4, seed=2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("ncy,nmr", [(1, 4), (3, 2), (2, 0)])
+def test_sap_matches_oracle(lat, prec, ncy, nmr):
+    eta = synth.gaussian_spinor(lat.dims, seed=3)
+    m0 = -0.2
+    ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0, eta, ncy, nmr, BC)
+    out = gpu_sap(lat, eta, m0, ncy, nmr, prec)
+    if nmr == 0:
+        assert np.max(np.abs(out)) == 0
+    else:
+        assert rel(out, ref) <= REL_TOL_SAP[prec]
+
+
+def test_sap_zero_cycles_is_zero(lat):
+    out = gpu_sap(lat, synth.gaussian_spinor(lat.dims, seed=4), 0.0, 0, 4, "f32")
+    assert np.max(np.abs(out)) == 0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sap_multi_rhs(lat, prec):
+    n = 3
+    eta = synth.gaussian_spinor(lat.dims, nrhs=n, seed=5)
+    m0 = np.array([-0.3, -0.1, 0.2])
+    out = gpu_sap(lat, eta, m0, 2, 4, prec, nrhs=n)
+    for r in range(n):
+        ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0[r], eta[r], 2, 4, BC)
+        assert rel(out[r], ref) <= REL_TOL_SAP[prec]
+        if prec == "f64":
+            assert np.array_equal(out[r], gpu_sap(lat, eta[r], m0[r], 2, 4, prec))
+
+
+def gpu_solve(lat, b, m0, sap_prec, nrhs=None, **kw):
+    from paper_1710_07041_amd import ddsap
+    import torch
+    n = 1 if nrhs is None else nrhs
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    p = ddsap.default_params()
+    p.sap_prec = ddsap.PREC[sap_prec]
+    for k, v in kw.items():
+        setattr(p, k, v)
+    st, info = lat.ctx.solve(m0, bd, xd, n, p, raise_on_fail=False)
+    return st, info, to_host(xd)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    """8^4, eps = 0.3, csw = 1, m0 = -0.2, Gaussian right-hand side, seed 0."""
+    return Lattice((8, 8, 8, 8), eps=0.3, csw=1.0, seed=0)
+
+
+@pytest.mark.parametrize("sap_prec", ["f64", "f32", "f16"])
+def test_solve_c1_residual_against_oracle(c1, sap_prec):
+    b = synth.gaussian_spinor(c1.dims, seed=0)
+    m0 = -0.2
+    st, info, x = gpu_solve(c1, b, m0, sap_prec)
+    assert st == 0 and info[0]["status"] == 0
+    r = b - oracle.apply_D(c1.dims, c1.U, c1.C, m0, x, BC)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert info[0]["rel_residual"] <= 1e-10
+
+
+def test_solve_mixed_vs_fp64_agree(c1):
+    b = synth.gaussian_spinor(c1.dims, seed=7)
+    _, _, x64 = gpu_solve(c1, b, -0.2, "f64")
+    _, _, x32 = gpu_solve(c1, b, -0.2, "f32")
+    assert rel(x32, x64) <= 1e-7
+
+
+def test_solve_multi_rhs_equals_solo(c1):
+    n = 4
+    b = synth.gaussian_spinor(c1.dims, nrhs=n, seed=8)
+    m0 = np.array([-0.2, -0.1, 0.0, 0.15])
+    st, info, x = gpu_solve(c1, b, m0, "f32", nrhs=n)
+    assert st == 0
+    for r in range(n):
+        res = b[r] - oracle.apply_D(c1.dims, c1.U, c1.C, m0[r], x[r], BC)
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10
+        _, _, xs = gpu_solve(c1, b[r], m0[r], "f32")
+        assert rel(x[r], xs) <= 1e-8
+
+
+def test_solve_point_sources(c1):
+    """The twelve spin-colour point sources, fused."""
+    b = synth.point_sources(c1.dims)
+    st, info, x = gpu_solve(c1, b, -0.2, "f32", nrhs=12)
+    assert st == 0
+    for r in range(12):
+        res = b[r] - oracle.apply_D(c1.dims, c1.U, c1.C, -0.2, x[r], BC)
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10
+
+
+def test_solve_error_paths(c1):
+    from paper_1710_07041_amd import ddsap
+    b = synth.gaussian_spinor(c1.dims, seed=1)
+    bad = b.copy()
+    bad[5, 0, 0] = np.inf
+    st, info, _ = gpu_solve(c1, bad, -0.2, "f32")
+    assert st == ddsap.DD_NAN
+    st, info, _ = gpu_solve(c1, b, -0.2, "f32", max_restarts=1, m=2)
+    assert st == ddsap.DD_NOT_CONVERGED and info[0]["status"] == ddsap.DD_NOT_CONVERGED
+    assert info[0]["iterations"] == 2
+    st, info, x = gpu_solve(c1, np.zeros_like(b), -0.2, "f32")
+    assert st == 0 and np.max(np.abs(x)) == 0
+
+
+def test_solve_warm_start(c1):
+    from paper_1710_07041_amd import ddsap
+    import torch
+    b = synth.gaussian_spinor(c1.dims, seed=2)
+    _, _, x = gpu_solve(c1, b, -0.2, "f32")
+    bd, xd = to_dev(b), to_dev(x)
+    st, info = c1.ctx.solve(-0.2, bd, xd, 1, ddsap.default_params())
+    assert st == 0 and info[0]["iterations"] == 0
