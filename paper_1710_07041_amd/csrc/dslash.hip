@@ -133,6 +133,8 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
 Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
                      int field_prec, const double *resid)
 {
+    if (!in || !out || !ctx->links[field_prec].p || !ctx->clover[field_prec].p)
+        return Status{DD_INVALID_ARG, "operator: missing buffer"};
     DArgs a = make_args(ctx, m0, nrhs);
     bool rs = resid != nullptr;
     if (in_prec == DD_F64 && out_prec == DD_F64 && field_prec == DD_F64)

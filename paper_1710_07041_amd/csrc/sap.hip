@@ -246,6 +246,8 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec)
 {
+    if (!eta || !psi || !ctx->links[prec].p || !ctx->clover[prec].p)
+        return Status{DD_INVALID_ARG, "SAP: missing buffer"};
     if (ncy == 0) {
         DD_HIP_TRY(hipMemsetAsync(psi, 0, spinor_bytes(ctx->g, prec, nrhs), ctx->stream));
         return Status::ok();

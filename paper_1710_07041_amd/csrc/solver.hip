@@ -393,13 +393,26 @@ Status combine(const Launch &L, double2 *x, int nv)
     return Status::ok();
 }
 
+Status alloc_base(dd_ctx *ctx, SolverWork *W, int nrhs, int m, int zprec);
+
 Status prepare(dd_ctx *ctx, int nrhs, int m, int sap_prec)
 {
     auto &Wp = ctx->work;
     int zprec = sap_prec == DD_F64 ? DD_F64 : DD_F32;
-    if (Wp && Wp->nrhs == nrhs && Wp->m >= m && Wp->zprec == zprec) return Status::ok();
-    Wp.reset(new SolverWork());
+    if (!(Wp && Wp->nrhs == nrhs && Wp->m >= m && Wp->zprec == zprec)) {
+        Wp.reset(new SolverWork());
+        DD_TRY(alloc_base(ctx, Wp.get(), nrhs, m, zprec));
+    }
+    // buffers that only some smoother precisions need; a workspace reused from
+    // a solve in another precision may lack them
     SolverWork *W = Wp.get();
+    if (sap_prec != DD_F64 && !W->lp.p) DD_TRY(W->lp.alloc((size_t)W->vlen * 2 * real_bytes(DD_F32)));
+    if (sap_prec == DD_F16 && !W->sapout.p) DD_TRY(W->sapout.alloc((size_t)W->vlen * 2 * real_bytes(DD_F16)));
+    return Status::ok();
+}
+
+Status alloc_base(dd_ctx *ctx, SolverWork *W, int nrhs, int m, int zprec)
+{
     W->nrhs = nrhs;
     W->m = m;
     W->zprec = zprec;
@@ -411,8 +424,6 @@ Status prepare(dd_ctx *ctx, int nrhs, int m, int sap_prec)
     DD_TRY(W->w.alloc(v64));
     DD_TRY(W->xb.alloc(v64));
     DD_TRY(W->bb.alloc(v64));
-    if (sap_prec != DD_F64) DD_TRY(W->lp.alloc((size_t)W->vlen * 2 * real_bytes(DD_F32))); // room for an FP32 fallback
-    if (sap_prec == DD_F16) DD_TRY(W->sapout.alloc((size_t)W->vlen * 2 * real_bytes(DD_F16)));
     DD_TRY(W->partial.alloc((size_t)W->G * nrhs * KMAX * 16));
     DD_TRY(W->res.alloc((size_t)nrhs * KMAX * 16));
     DD_TRY(W->res2.alloc((size_t)nrhs * KMAX * 16));

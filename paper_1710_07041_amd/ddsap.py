@@ -17,6 +17,11 @@ import numpy as np
 _PKG = Path(__file__).resolve().parent
 LIB_PATH = Path(os.environ.get("DDSAP_LIB", _PKG / "libddsap.so"))
 
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+# Loading torch first makes this library bind to that one runtime instead of
+# pulling a second copy (and a second HSA runtime) into the process.
+import torch  # noqa: E402,F401
+
 if not LIB_PATH.exists():
     raise ImportError(f"libddsap.so not found at {LIB_PATH}; build it with paper_1710_07041_amd/build.py "
                       "(or __graft_entry__.build())")
