@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark: Dslash GB/s against the HBM roofline and time-to-1e-10 of the
+SAP-preconditioned FGMRES solve (mixed precision vs FP64) on one MI355X.
+
+One step = one complete solve of the workload: FP64 FGMRES(20) outer iteration
+(operator, CGS2 orthogonalisation, reductions, true-residual restarts) with
+the red-black SAP smoother (4^4 blocks, 4 MR steps, 4 cycles) in FP32 --
+every stage of the hot path.  Inputs (gauge field, clover, right-hand side)
+are resident in HBM before the timed region starts.
+
+The JSON line reports
+  value            algorithmic GB/s of the FP64 Wilson-clover operator launches
+                   inside the timed solves (HIP events on the launch stream);
+  roofline         the kernel class that dominates the step time;
+  roofline_dslash  the operator itself, against 8 TB/s HBM;
+  time_to_solution mixed (FP32 SAP) vs the FP64 GPU path (FP64 SAP);
+  cpu_baseline     the FP64 CPU oracle on a bounded sample, same unit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VEC_TFLOPS = 78.6         # MI355X vector FP64
+FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (published, packed)
+
+WORKLOADS = {
+    # name: dims, eps, m0, csw, smoother precision, nrhs, source
+    "c2": dict(dims=(32, 32, 32, 64), eps=0.5, m0=-0.35, csw=1.0, sap="f32", nrhs=1, source="gaussian",
+               text="32^3x64, random SU(3) eps=0.5, csw=1.0, m0=-0.35, 1 Gaussian RHS, SAP FP32 4^4 blocks "
+                    "nmr=4 ncy=4, FGMRES(20) FP64, tol 1e-10"),
+    "c1": dict(dims=(8, 8, 8, 8), eps=0.3, m0=-0.2, csw=1.0, sap="f32", nrhs=1, source="gaussian",
+               text="8^4, eps=0.3, csw=1.0, m0=-0.2, 1 Gaussian RHS, 4^4 blocks, FGMRES(20), tol 1e-10"),
+    "c3": dict(dims=(48, 48, 48, 96), eps=0.6, m0=-0.38, csw=1.0, sap="f16", nrhs=1, source="gaussian",
+               text="48^3x96, eps=0.6, m0=-0.38, SAP FP16 storage / FP32 arithmetic, FGMRES(20) FP64, tol 1e-10"),
+    "c4": dict(dims=(32, 32, 32, 64), eps=0.5, m0=-0.35, csw=1.0, sap="f32", nrhs=12, source="point",
+               text="32^3x64, 12 point-source RHS (spin x colour), fused multi-RHS SAP FP32, FGMRES(20) FP64 "
+                    "per RHS, tol 1e-10"),
+}
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp64-steps", type=int, default=1, help="FP64-smoother solves timed alongside")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle's operator on a bounded sample: the 16^3x32 lattice (the
+    paper's single-chip lattice) with the workload's field recipe."""
+    import oracle
+    from paper_1710_07041_amd import synth
+    dims = (16, 16, 16, 32)
+    U = synth.random_su3_links(dims, 0.5, seed=0)
+    C = oracle.clover_field(dims, U, 1.0)
+    psi = synth.gaussian_spinor(dims, seed=1)
+    V = synth.volume(dims)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.apply_D(dims, U, C, -0.35, psi)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = (time.perf_counter() - t0) / n
+    return {"value": round(V * 192 * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle Wilson-clover operator on a 16^3x32 lattice (eps=0.5, csw=1), {n} applications "
+                      f"in {dt * n:.1f} s; algorithmic 192 reals/site as on the GPU",
+            "ms_per_apply": round(dt * 1e3, 3)}
+
+
+def make_rhs(w, V, dims):
+    from paper_1710_07041_amd import synth
+    if w["source"] == "point":
+        return synth.point_sources(dims)
+    b = synth.gaussian_spinor(dims, seed=0)
+    return b[None] if w["nrhs"] == 1 else np.stack([synth.gaussian_spinor(dims, seed=k) for k in range(w["nrhs"])])
+
+
+def roofline_entry(name, st, peak_gbs=HBM_PEAK_GBS):
+    avg_ms = st["total_ms"] / st["launches"]
+    bytes_per = st["bytes"] / st["launches"]
+    flops_per = st["flops"] / st["launches"]
+    gbs = bytes_per / (avg_ms * 1e-3) / 1e9
+    tfl = flops_per / (avg_ms * 1e-3) / 1e12
+    return {"kernel": name, "avg_ms": round(avg_ms, 4), "launches": st["launches"], "bytes_per_launch": bytes_per,
+            "flops_per_launch": flops_per, "gbs": round(gbs, 1), "tflops": round(tfl, 2),
+            "frac_hbm": round(gbs / peak_gbs, 4)}
+
+
+def dslash_standalone(ctx, dims, reps=20):
+    """The operator alone in every precision (and 12 fused right-hand sides in
+    FP32), timed with HIP events on the context stream: GB/s vs the roofline."""
+    import torch
+    from paper_1710_07041_amd import synth
+    res = {}
+    for prec, n in (("f64", 1), ("f32", 1), ("f16", 1), ("f32", 12)):
+        psi = synth.gaussian_spinor(dims, nrhs=n, seed=3)
+        x = torch.from_numpy(psi).to("cuda")
+        xb, yb = ctx.empty_blocked(prec, n), ctx.empty_blocked(prec, n)
+        ctx.pack(x, xb, prec, n)
+        del x, psi
+        m0 = np.full(n, -0.35)
+        ctx.apply_D(m0, xb, yb, prec, n)
+        ctx.profile_enable(True)
+        for _ in range(reps):
+            ctx.apply_D(m0, xb, yb, prec, n)
+        st = ctx.profile_read()
+        ctx.profile_enable(False)
+        (name, v), = st.items()
+        e = roofline_entry(name, v)
+        res[f"{prec}_x{n}"] = {"gbs": e["gbs"], "frac": e["frac_hbm"], "avg_ms": e["avg_ms"],
+                               "gflops": round(e["tflops"] * 1e3, 1)}
+        del xb, yb
+        torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver does not shard across GPUs "
+              "in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_07041_amd import ddsap, synth
+
+    w = WORKLOADS[args.workload]
+    dims, nrhs = w["dims"], w["nrhs"]
+    V = synth.volume(dims)
+    torch.cuda.set_device(0)
+    log(f"workload {args.workload}: {w['text']}")
+    t0 = time.perf_counter()
+    U = synth.random_su3_links(dims, w["eps"], seed=0)
+    b = make_rhs(w, V, dims)
+    log(f"fields generated in {time.perf_counter() - t0:.1f} s")
+    ctx = ddsap.Context(dims, (1, 1, 1, -1))
+    ctx.set_gauge(U, w["csw"])
+    del U
+    bd = torch.from_numpy(np.ascontiguousarray(b)).to("cuda")
+    xd = torch.zeros_like(bd)
+    m0 = np.full(nrhs, w["m0"])
+
+    def params(sap):
+        p = ddsap.default_params()
+        p.sap_prec = ddsap.PREC[sap]
+        return p
+
+    def one_solve(sap):
+        xd.zero_()
+        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap), raise_on_fail=False)
+        if st != ddsap.DD_OK:
+            raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
+        return info
+
+    for i in range(args.warmup):
+        info = one_solve(w["sap"])
+        log(f"warmup {i}: {info[0]['iterations']} iterations, residual {info[0]['rel_residual']:.2e}")
+
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(one_solve(w["sap"]))
+        log(f"step {i}: {infos[-1][0]['iterations']} iterations, residual {infos[-1][0]['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+
+    # FP64 GPU path (FP64 smoother), same algorithm, timed alongside
+    t64 = None
+    info64 = None
+    if args.fp64_steps > 0:
+        one_solve("f64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.fp64_steps):
+            info64 = one_solve("f64")
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / args.fp64_steps
+        log(f"fp64 path: {info64[0]['iterations']} iterations, {t64 * 1e3:.1f} ms")
+
+    standalone = dslash_standalone(ctx, dims)
+    log(f"operator alone: {standalone}")
+
+    # operator launches inside the timed solves
+    dsl = {k: v for k, v in prof.items() if k in ("dslash_f64", "dslash_f32in_f64")}
+    d_bytes = sum(v["bytes"] for v in dsl.values())
+    d_ms = sum(v["total_ms"] for v in dsl.values())
+    d_launch = sum(v["launches"] for v in dsl.values())
+    dslash_gbs = d_bytes / (d_ms * 1e-3) / 1e9
+    main_cls = max(dsl, key=lambda k: dsl[k]["total_ms"])
+    rd = roofline_entry(main_cls, dsl[main_cls])
+
+    total_ms = sum(v["total_ms"] for v in prof.values())
+    dom = max(prof, key=lambda k: prof[k]["total_ms"])
+    rdom = roofline_entry(dom, prof[dom])
+    if dom.startswith("sap"):
+        # smoother: arithmetic intensity above the FP32 ridge -> priced against the vector ALU peak
+        roof = {"bound": "alu", "kernel": dom, "achieved": rdom["tflops"], "peak": FP32_VEC_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(rdom["tflops"] / FP32_VEC_TFLOPS, 4), "traffic": None,
+                "hbm_gbs": rdom["gbs"], "hbm_frac": rdom["frac_hbm"], "avg_ms": rdom["avg_ms"]}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": rdom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": rdom["frac_hbm"], "traffic": None, "avg_ms": rdom["avg_ms"]}
+
+    breakdown = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3),
+                     "share": round(v["total_ms"] / total_ms, 4),
+                     "gbs": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] > 0 else None}
+                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+
+    out = {
+        "metric": "Dslash GB/s & % HBM roofline; time-to-1e-10 SAP-FGMRES solve (mixed vs FP64)",
+        "value": round(dslash_gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": w["text"], "lattice": "x".join(map(str, dims)), "nrhs": nrhs,
+                   "smoother": w["sap"], "parallelism": "single GPU"},
+        "roofline": roof,
+        "roofline_dslash": {"bound": "hbm", "kernel": main_cls, "achieved": rd["gbs"], "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": rd["frac_hbm"], "traffic": None, "avg_ms": rd["avg_ms"],
+                            "bytes_per_launch": rd["bytes_per_launch"]},
+        "dslash_frac_hbm": round(dslash_gbs / HBM_PEAK_GBS, 4),
+        "dslash_standalone": standalone,
+        "time_to_solution_s": {"mixed": round(t_mixed, 4), "fp64": None if t64 is None else round(t64, 4),
+                               "fp64_over_mixed": None if t64 is None else round(t64 / t_mixed, 3)},
+        "iterations": {"mixed": infos[-1][0]["iterations"],
+                       "fp64": None if info64 is None else info64[0]["iterations"]},
+        "final_rel_residual": max(i["rel_residual"] for i in infos[-1]),
+        "kernels": breakdown,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

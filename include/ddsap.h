@@ -173,6 +173,31 @@ dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int 
 dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs,
                    const dd_params *params, dd_solve_info *info);
 
+/* ---------------------------------------------------------------------------
+ * Measurement (optional; used to price kernels against the hardware roofline)
+ * ---------------------------------------------------------------------------
+ * Per kernel class: launches, summed duration of the launches measured with
+ * HIP events recorded on the context's stream, and the algorithmic bytes and
+ * flops those launches represent (the method's data volume -- links, clover
+ * and spinors each counted once per launch -- not the bytes the hardware
+ * moved).  Counting conventions: one operator application is 1848 flops per
+ * site and right-hand side; one MR step is 2184 flops per site. */
+typedef struct {
+    char name[32];
+    long launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} dd_kernel_stat;
+
+/* Switch event timing on (1) or off (0); switching on clears the counters. */
+dd_status dd_profile_enable(dd_ctx *ctx, int enable);
+
+/* Synchronise the context's stream, fold in every finished measurement and
+ * copy up to max classes with at least one launch into out (host array).
+ * Returns the number of entries written, or -1 on error. */
+int dd_profile_read(dd_ctx *ctx, dd_kernel_stat *out, int max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -298,4 +298,38 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
     });
 }
 
+dd_status dd_profile_enable(dd_ctx *ctx, int enable)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->prof.reset();
+        ctx->prof.on = enable != 0;
+        return dd::Status::ok();
+    });
+}
+
+int dd_profile_read(dd_ctx *ctx, dd_kernel_stat *out, int max)
+{
+    if (!ctx || (!out && max > 0)) return -1;
+    if (hipSetDevice(ctx->device) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "dd_profile_read: stream synchronisation failed";
+        return -1;
+    }
+    ctx->prof.resolve();
+    int n = 0;
+    for (int k = 0; k < dd::K_NCLASS && n < max; ++k) {
+        if (ctx->prof.launches[k] == 0) continue;
+        dd_kernel_stat &st = out[n++];
+        std::memset(&st, 0, sizeof(st));
+        std::strncpy(st.name, dd::kclass_name(k), sizeof(st.name) - 1);
+        st.launches = ctx->prof.launches[k];
+        st.total_ms = ctx->prof.ms[k];
+        st.bytes = ctx->prof.bytes[k];
+        st.flops = ctx->prof.flops[k];
+    }
+    return n;
+}
+
 } // extern "C"

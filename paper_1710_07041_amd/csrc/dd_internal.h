@@ -70,6 +70,45 @@ struct GeomHost {
     int bcs[4];
 };
 
+// Kernel classes timed by the optional profiler (HIP events on the context
+// stream around every launch), with the algorithmic bytes and flops of each
+// launch as defined by the method (not the bytes the hardware moved).
+enum KClass {
+    K_DSLASH_F64 = 0, K_DSLASH_F32IN_F64, K_DSLASH_F32, K_DSLASH_F16, K_DSLASH_BLOCK,
+    K_SAP_F64, K_SAP_F32, K_SAP_F16,
+    K_CGS_DOTS, K_CGS_UPDATE, K_CGS_NORMALIZE, K_REDUCE, K_COMBINE, K_CONVERT, K_PACK,
+    K_NCLASS
+};
+const char *kclass_name(int k);
+
+struct Prof {
+    bool on = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+        double bytes, flops;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    long launches[K_NCLASS] = {};
+    double ms[K_NCLASS] = {}, bytes[K_NCLASS] = {}, flops[K_NCLASS] = {};
+    ~Prof();
+    hipEvent_t get();
+    void resolve(); // caller has synchronised the stream
+    void reset();
+};
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    Prof *p;
+    hipStream_t st;
+    int cls;
+    double bytes, flops;
+    hipEvent_t a = nullptr;
+    ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl);
+    ~ProfScope();
+};
+
 struct SolverWork; // solver.hip
 struct SolverWorkDeleter {
     void operator()(SolverWork *w) const; // solver.hip
@@ -88,6 +127,7 @@ struct dd_ctx {
     dd::DevBuf colour_blocks[2]; // int block ids of each colour, XCD-friendly order
     int ncolour[2] = {0, 0};
     std::string err;
+    dd::Prof prof;
     std::unique_ptr<dd::SolverWork, dd::SolverWorkDeleter> work;
 };
 

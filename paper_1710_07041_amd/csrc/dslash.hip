@@ -120,6 +120,11 @@ template <typename SI, typename SO, typename SF, typename A, bool RESID>
 Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_prec, const void *resid)
 {
     int grid = ctx->g.nblocks * a.nrhs;
+    const double V = (double)ctx->g.V, n = a.nrhs;
+    const double by = V * (144.0 * sizeof(SF) + 24.0 * n * (sizeof(SI) + sizeof(SO) * (RESID ? 2 : 1)));
+    int cls = sizeof(SF) == 8 ? (sizeof(SI) == 8 ? K_DSLASH_F64 : K_DSLASH_F32IN_F64)
+                              : (sizeof(SF) == 4 ? K_DSLASH_F32 : K_DSLASH_F16);
+    ProfScope ps(ctx->prof, ctx->stream, cls, by, 1848.0 * V * n);
     k_dslash<SI, SO, SF, A, false, RESID><<<grid, BS, 0, ctx->stream>>>(
         static_cast<const vec2_t<SI> *>(in), static_cast<vec2_t<SO> *>(out),
         static_cast<const vec2_t<SF> *>(ctx->links[field_prec].p), static_cast<const vec2_t<SF> *>(ctx->clover[field_prec].p),
@@ -153,6 +158,7 @@ Status launch_dslash_block(dd_ctx *ctx, double m0, int block_id, const void *in,
 {
     DArgs a = make_args(ctx, &m0, 1);
     a.block_id = block_id;
+    ProfScope ps(ctx->prof, ctx->stream, K_DSLASH_BLOCK, 256.0 * (144.0 + 48.0) * real_bytes(prec), 1848.0 * 256);
     if (prec == DD_F64)
         k_dslash<double, double, double, double, true, false><<<1, BS, 0, ctx->stream>>>(
             static_cast<const double2 *>(in), static_cast<double2 *>(out), ctx->links[DD_F64].as<double2>(),

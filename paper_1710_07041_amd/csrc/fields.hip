@@ -290,6 +290,7 @@ Status set_clover_canon(dd_ctx *ctx, const double *C_dev)
 Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs)
 {
     const GeomHost &g = ctx->g;
+    ProfScope ps(ctx->prof, ctx->stream, K_PACK, (double)g.V * nrhs * 24.0 * (8 + real_bytes(prec)), 0.0);
     CanonGeom cg = canon_geom(g);
     int grid = g.nblocks * nrhs;
     const double2 *in = reinterpret_cast<const double2 *>(canon);
@@ -306,6 +307,7 @@ Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, in
 Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs)
 {
     const GeomHost &g = ctx->g;
+    ProfScope ps(ctx->prof, ctx->stream, K_PACK, (double)g.V * nrhs * 24.0 * (8 + real_bytes(prec)), 0.0);
     CanonGeom cg = canon_geom(g);
     int grid = g.nblocks * nrhs;
     double2 *out = reinterpret_cast<double2 *>(canon);

@@ -1,0 +1,83 @@
+// Optional per-kernel-class timing: HIP events recorded on the context stream
+// around each launch, resolved after the stream has been synchronised.
+#include "dd_internal.h"
+
+namespace dd {
+
+const char *kclass_name(int k)
+{
+    static const char *names[K_NCLASS] = {
+        "dslash_f64", "dslash_f32in_f64", "dslash_f32", "dslash_f16", "dslash_block",
+        "sap_sweep_f64", "sap_sweep_f32", "sap_sweep_f16",
+        "cgs_dots", "cgs_update_dots", "cgs_update_normalize", "reduce", "combine", "convert", "pack",
+    };
+    return (k >= 0 && k < K_NCLASS) ? names[k] : "?";
+}
+
+Prof::~Prof()
+{
+    for (auto &r : pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+hipEvent_t Prof::get()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void Prof::resolve()
+{
+    for (auto &r : pending) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            launches[r.cls] += 1;
+            ms[r.cls] += t;
+            bytes[r.cls] += r.bytes;
+            flops[r.cls] += r.flops;
+        }
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+}
+
+void Prof::reset()
+{
+    resolve();
+    for (int k = 0; k < K_NCLASS; ++k) {
+        launches[k] = 0;
+        ms[k] = bytes[k] = flops[k] = 0.0;
+    }
+}
+
+ProfScope::ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl)
+    : p(pr.on ? &pr : nullptr), st(s), cls(c), bytes(by), flops(fl)
+{
+    if (!p) return;
+    a = p->get();
+    if (a) (void)hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!p || !a) return;
+    hipEvent_t b = p->get();
+    if (!b) {
+        p->pool.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, st);
+    p->pending.push_back({cls, a, b, bytes, flops});
+}
+
+} // namespace dd

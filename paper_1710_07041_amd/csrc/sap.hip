@@ -235,6 +235,12 @@ __global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ 
 template <typename S, typename A, bool REGCLOV>
 Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 {
+    // algorithmic traffic of one colour sweep: links + clover once, eta, psi
+    // (read only when nonzero) and psi written, per swept site and rhs
+    const double sites = 256.0 * a.nblk, sb = (double)sizeof(S), n = a.nrhs;
+    const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0)));
+    const double fl = sites * n * (a.nmr * 2184.0 + (a.mode == 2 ? 1848.0 : 0.0));
+    ProfScope ps(ctx->prof, ctx->stream, prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16, by, fl);
     k_sap_sweep<S, A, REGCLOV><<<a.nblk, BS, 0, ctx->stream>>>(
         static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
         static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p), a);

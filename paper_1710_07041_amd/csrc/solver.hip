@@ -19,9 +19,9 @@
 //   reproducible); one small device-to-host copy per step feeds the host-side
 //   Givens rotations and the stopping test.  Restarts recompute the true
 //   residual b - D x in FP64 on the device; the solve stops only on it.
-// Right-hand sides that have converged (or finished their cycle) are masked:
-// their basis vectors become zero, so the fused launches carry them at no
-// numerical effect until the next restart boundary.
+// Right-hand sides that have converged are masked at the restart boundary
+// (zero basis vectors); one that finishes its cycle early rides along in the
+// fused launches until the restart, its extra columns never read.
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -316,10 +316,13 @@ struct Launch {
 
 #define DD_BUCKETS(X) X(1) X(4) X(8) X(12) X(16) X(22) X(33)
 
+double vec64_bytes(const Launch &L) { return (double)L.W->vlen * 16.0; }
+
 Status dots(const Launch &L, const double2 *V, int nv, const double2 *w)
 {
     SolverWork *W = L.W;
     int K = KMAX;
+    ProfScope ps(L.ctx->prof, L.ctx->stream, K_CGS_DOTS, vec64_bytes(L) * (nv + 1), 8.0 * W->vlen * nv);
     switch (pick_bucket(nv)) {
 #define C(N) case N: k_dots<N><<<L.grid(), TPB, 0, L.ctx->stream>>>(V, W->vlen, nv, w, W->partial.as<double2>(), L.ctx->g.nblocks, W->nrhs, K); break;
         DD_BUCKETS(C)
@@ -332,6 +335,7 @@ Status dots(const Launch &L, const double2 *V, int nv, const double2 *w)
 Status update_dots(const Launch &L, const double2 *V, int nv, const double2 *h, double2 *w)
 {
     SolverWork *W = L.W;
+    ProfScope ps(L.ctx->prof, L.ctx->stream, K_CGS_UPDATE, vec64_bytes(L) * (nv + 2), 16.0 * W->vlen * nv + 4.0 * W->vlen);
     switch (pick_bucket(nv)) {
 #define C(N) case N: k_update_dots<N><<<L.grid(), TPB, 0, L.ctx->stream>>>(V, W->vlen, nv, h, w, W->partial.as<double2>(), L.ctx->g.nblocks, W->nrhs, KMAX, KMAX); break;
         DD_BUCKETS(C)
@@ -346,6 +350,8 @@ Status update_normalize_t(const Launch &L, const double2 *V, int nv, const doubl
                           double2 *vnext, void *lp, bool fp16)
 {
     SolverWork *W = L.W;
+    ProfScope ps(L.ctx->prof, L.ctx->stream, K_CGS_NORMALIZE,
+                 vec64_bytes(L) * (nv + 2) + (lp ? (double)W->vlen * 2 * sizeof(SL) : 0.0), 8.0 * W->vlen * (nv + 1));
     switch (pick_bucket(nv)) {
 #define C(N) case N: k_update_normalize<N, SL><<<L.grid(), TPB, 0, L.ctx->stream>>>(V, W->vlen, nv, res, KMAX, w, vnext, static_cast<vec2_t<SL> *>(lp), W->scl.as<double>(), W->active.as<int>(), fp16 ? 1 : 0, L.ctx->g.nblocks, W->nrhs); break;
         DD_BUCKETS(C)
@@ -367,6 +373,7 @@ Status update_normalize(const Launch &L, const double2 *V, int nv, const double2
 Status reduce(const Launch &L, int nslots, int kmax_slot, double2 *out)
 {
     dim3 grid(nslots, L.W->nrhs);
+    ProfScope ps(L.ctx->prof, L.ctx->stream, K_REDUCE, (double)L.W->G * L.W->nrhs * nslots * 16.0, 0.0);
     k_reduce<<<grid, TPB, 0, L.ctx->stream>>>(L.W->partial.as<double2>(), out, L.W->G, L.W->nrhs, KMAX, kmax_slot);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
@@ -376,6 +383,8 @@ Status combine(const Launch &L, double2 *x, int nv)
 {
     SolverWork *W = L.W;
     const double2 *y = W->y.as<double2>();
+    ProfScope ps(L.ctx->prof, L.ctx->stream, K_COMBINE,
+                 vec64_bytes(L) * 2 + (double)W->vlen * 2 * real_bytes(W->zprec) * nv, 8.0 * W->vlen * nv);
     if (W->zprec == DD_F64) {
         switch (pick_bucket(nv)) {
 #define C(N) case N: k_combine<N, double><<<L.grid(), TPB, 0, L.ctx->stream>>>(x, W->Z.as<double2>(), W->vlen, nv, y, W->active.as<int>(), L.ctx->g.nblocks, W->nrhs); break;
@@ -565,6 +574,7 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
                 DD_TRY(run_sap(ctx, m0, nrhs, W->lp.p, Zj(j), p.ncy, p.nmr, DD_F32));
             } else {
                 DD_TRY(run_sap(ctx, m0, nrhs, W->lp.p, W->sapout.p, p.ncy, p.nmr, DD_F16));
+                ProfScope ps(ctx->prof, st, K_CONVERT, (double)vlen * 12.0, 2.0 * vlen);
                 k_unscale<<<L.grid(), TPB, 0, st>>>(W->sapout.as<__half2>(), reinterpret_cast<float2 *>(Zj(j)),
                                                     W->scl.as<double>(), ctx->g.nblocks, nrhs);
                 DD_HIP_TRY(hipGetLastError());
@@ -629,10 +639,10 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
                 break;
             }
             if (!cont) break;
+            // A right-hand side that left its cycle keeps riding along in the
+            // fused launches until the restart: its columns are never read
+            // again (the host skips it, combine stops at its cycle length).
             DD_HIP_TRY(hipMemcpyAsync(W->active.p, W->h_active, (size_t)nrhs * 4, hipMemcpyHostToDevice, st));
-            // an inactive right-hand side must not feed a stale vector to the
-            // next step: re-run its normalisation with the new mask
-            DD_TRY(update_normalize(L, V, nv, W->res2.as<double2>(), w, V + (long)nv * vlen, sap_prec));
         }
         // y = R^{-1} g per right-hand side, x += Z y
         int maxlen = 0;

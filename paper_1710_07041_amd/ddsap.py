@@ -38,7 +38,7 @@ DD_MAX_RHS = 16
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
-    "dd_apply_D_block", "dd_sap", "dd_solve",
+    "dd_apply_D_block", "dd_sap", "dd_solve", "dd_profile_enable", "dd_profile_read",
 ]
 
 
@@ -50,6 +50,11 @@ class dd_params(ctypes.Structure):
 class dd_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("sap_calls", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class dd_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_long), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 _vp, _ip, _d, _i, _l, _sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int, \
@@ -71,6 +76,8 @@ _sigs = {
     "dd_apply_D_block": ([_vp, _d, _l, _vp, _vp, _i], _i),
     "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
+    "dd_profile_enable": ([_vp, _i], _i),
+    "dd_profile_read": ([_vp, ctypes.POINTER(dd_kernel_stat), _i], _i),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -194,3 +201,15 @@ class Context:
         if raise_on_fail and st not in (DD_OK,):
             raise DDError(st, _lib.dd_last_error(self._h).decode())
         return st, out
+
+    def profile_enable(self, on=True):
+        self._check(_lib.dd_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel class: {launches, total_ms, bytes, flops}} (synchronises)."""
+        buf = (dd_kernel_stat * 64)()
+        n = _lib.dd_profile_read(self._h, buf, 64)
+        if n < 0:
+            raise DDError(DD_HIP_ERROR, _lib.dd_last_error(self._h).decode())
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                       "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(n)}
