@@ -184,6 +184,28 @@ __device__ __forceinline__ void su3_mul_adj(const cx<A> U[9], const cx<A> h[6], 
         }
 }
 
+// acc += (diag + C_k) p for one packed Hermitian 6x6 chiral half (18 slots);
+// p and acc point at that half's six components
+template <typename A>
+__device__ __forceinline__ void clover_half_mac(const cx<A> c[18], A diag, const cx<A> x[6], cx<A> acc[6])
+{
+    A d[6] = {c[0].re, c[0].im, c[1].re, c[1].im, c[2].re, c[2].im};
+    cx<A> y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] = (d[i] + diag) * x[i];
+    int e = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+            cmac(y[i], c[e], x[j]);
+            cmacc(y[j], c[e], x[i]);
+            ++e;
+        }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] = acc[i] + y[i];
+}
+
 // acc += (diag + C) p, C = two packed Hermitian 6x6 halves (36 slots)
 template <typename A>
 __device__ __forceinline__ void clover_mac(const cx<A> cl[36], A diag, const cx<A> p[12], cx<A> acc[12])

@@ -86,13 +86,19 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
     for (int c = 0; c < 12; ++c) acc[c] = mk<A>(0, 0);
     hops<BLOCKONLY, SI, SF, A>(in, links, a, b, bc, r, s, acc);
     const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
-    cx<A> psi[12], cl[36];
+    const A diag = (A)(4.0 + a.m0[r]);
+    // one chiral half at a time: halves the registers the clover needs
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+        cx<A> psi[6], cl[18];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(in + sp + c * BS);
-    const vec2_t<SF> *cp = clov + (long)b * 36 * BS + s;
+        for (int c = 0; c < 6; ++c) psi[c] = ldc<A>(in + sp + (6 * k + c) * BS);
+        const vec2_t<SF> *cp = clov + ((long)b * 36 + 18 * k) * BS + s;
 #pragma unroll
-    for (int e = 0; e < 36; ++e) cl[e] = ldc<A>(cp + e * BS);
-    clover_mac(cl, (A)(4.0 + a.m0[r]), psi, acc);
+        for (int e = 0; e < 18; ++e) cl[e] = ldc<A>(cp + e * BS);
+        if (k == 0) clover_half_mac(cl, diag, psi, acc);
+        else clover_half_mac(cl, diag, psi, acc + 6);
+    }
     if (RESID) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) stc(out + sp + c * BS, ldc<A>(resid + sp + c * BS) - acc[c]);

@@ -43,8 +43,86 @@ template <typename A> struct Lds {
     A red[4][4];
 };
 
-template <int MU, typename A>
-__device__ __forceinline__ void exchange_hop(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
+// Direction-dispatched spin algebra for run-time loops over mu (a switch on a
+// uniform value; each case is the compile-time specialisation).
+template <typename A> __device__ __forceinline__ void proj_m(int mu, const cx<A> v[12], cx<A> h[6])
+{
+    switch (mu) {
+    case 0: proj_minus<0>(v, h); break;
+    case 1: proj_minus<1>(v, h); break;
+    case 2: proj_minus<2>(v, h); break;
+    default: proj_minus<3>(v, h); break;
+    }
+}
+template <typename A> __device__ __forceinline__ void proj_p(int mu, const cx<A> v[12], cx<A> h[6])
+{
+    switch (mu) {
+    case 0: proj_plus<0>(v, h); break;
+    case 1: proj_plus<1>(v, h); break;
+    case 2: proj_plus<2>(v, h); break;
+    default: proj_plus<3>(v, h); break;
+    }
+}
+template <typename A> __device__ __forceinline__ void recon_m(int mu, cx<A> q[12], const cx<A> t[6], A k)
+{
+    switch (mu) {
+    case 0: recon_minus<0>(q, t, k); break;
+    case 1: recon_minus<1>(q, t, k); break;
+    case 2: recon_minus<2>(q, t, k); break;
+    default: recon_minus<3>(q, t, k); break;
+    }
+}
+template <typename A> __device__ __forceinline__ void recon_p(int mu, cx<A> q[12], const cx<A> t[6], A k)
+{
+    switch (mu) {
+    case 0: recon_plus<0>(q, t, k); break;
+    case 1: recon_plus<1>(q, t, k); break;
+    case 2: recon_plus<2>(q, t, k); break;
+    default: recon_plus<3>(q, t, k); break;
+    }
+}
+
+// Where the per-site fields live during a sweep: in registers for the whole
+// sweep, or re-read (from L2: one block's fields stay resident while its
+// workgroup runs) at every block application.
+template <bool REGLINKS, bool REGCLOV, int WAVES> struct Residency {
+    static constexpr bool links = REGLINKS, clover = REGCLOV;
+    static constexpr int waves = WAVES;
+};
+
+template <bool REG, typename S, typename A>
+__device__ __forceinline__ void get_link(const cx<A> Ur[4][9], const vec2_t<S> *__restrict__ links, int b, int s,
+                                         int mu, cx<A> U[9])
+{
+    if (REG) {
+        switch (mu) {
+        case 0:
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = Ur[0][e];
+            break;
+        case 1:
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 1 : 0][e];
+            break;
+        case 2:
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 2 : 0][e];
+            break;
+        default:
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 3 : 0][e];
+            break;
+        }
+    } else {
+        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+    }
+}
+
+// One direction of the LDS exchange with the link given in registers.
+template <int MU, typename S, typename A>
+__device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
                                              const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
 {
     cx<A> h[6], t[6];
@@ -63,72 +141,123 @@ __device__ __forceinline__ void exchange_hop(Lds<A> &L, const Geom &g, int b, co
 #pragma unroll
         for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
         su3_mul(U, h, t);
-        recon_minus<MU>(q, t, (A)(-0.5 * sign));
+        recon_minus<MU>(q, t, (A)(sign > 0 ? -0.5f : 0.5f));
     }
     neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
     if (inb) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
-        recon_plus<MU>(q, t, (A)(-0.5 * sign));
+        recon_plus<MU>(q, t, (A)(sign > 0 ? -0.5f : 0.5f));
     }
     __syncthreads();
 }
 
-// q = D_BB v on the block (all threads of the workgroup take part)
-template <typename S, typename A, bool REGCLOV>
+// q = D_BB v on the block (all threads of the workgroup take part).  The
+// loops over clover halves and directions are kept as loops so that only one
+// step's loads are in flight per thread (unrolled, the compiler hoists them
+// all and spills).
+template <typename S, typename A, typename RES>
 __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
-                                            const cx<A> U[4][9], const cx<A> cl[36],
+                                            const cx<A> Ur[RES::links ? 4 : 1][9], const cx<A> cl[36],
+                                            const vec2_t<S> *__restrict__ links_g,
                                             const vec2_t<S> *__restrict__ clov_g, A diag, const cx<A> v[12],
                                             cx<A> q[12])
 {
 #pragma unroll
     for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
-    if (REGCLOV) {
+    if (RES::clover) {
         clover_mac(cl, diag, v, q);
     } else {
-        cx<A> c2[36];
-        const vec2_t<S> *cp = clov_g + (long)b * 36 * BS + s;
+#pragma unroll 1
+        for (int k = 0; k < 2; ++k) {
+            cx<A> c2[18];
+            const vec2_t<S> *cp = clov_g + ((long)b * 36 + 18 * k) * BS + s;
 #pragma unroll
-        for (int e = 0; e < 36; ++e) c2[e] = ldc<A>(cp + e * BS);
-        clover_mac(c2, diag, v, q);
+            for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
+            if (k == 0) clover_half_mac<A>(c2, diag, v, q);
+            else clover_half_mac<A>(c2, diag, v + 6, q + 6);
+        }
     }
-    exchange_hop<0>(L, g, b, bc, s, U[0], v, q);
-    exchange_hop<1>(L, g, b, bc, s, U[1], v, q);
-    exchange_hop<2>(L, g, b, bc, s, U[2], v, q);
-    exchange_hop<3>(L, g, b, bc, s, U[3], v, q);
+    if constexpr (RES::links) {
+        // links already in registers: no loads to hoist, unroll the directions
+        exchange_dir<0, S, A>(L, g, b, bc, s, Ur[0], v, q);
+        exchange_dir<1, S, A>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
+        exchange_dir<2, S, A>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
+        exchange_dir<3, S, A>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        return;
+    }
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<A> U[9], h[6], t[6];
+        get_link<RES::links, S, A>(Ur, links_g, b, s, mu, U);
+        proj_m(mu, v, h);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L.hf[c][s] = h[c];
+        proj_p(mu, v, h);
+        su3_mul_adj(U, h, t);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L.hb[c][s] = t[c];
+        __syncthreads();
+        int bn, sn, sign;
+        bool inb;
+        neighbour_rt(g, b, bc, s, mu, +1, bn, sn, sign, inb);
+        if (inb) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
+            su3_mul(U, h, t);
+            recon_m(mu, q, t, (A)(sign > 0 ? -0.5f : 0.5f));
+        }
+        neighbour_rt(g, b, bc, s, mu, -1, bn, sn, sign, inb);
+        if (inb) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
+            recon_p(mu, q, t, (A)(sign > 0 ? -0.5f : 0.5f));
+        }
+        __syncthreads();
+    }
 }
 
-// hops of site s whose neighbour lies outside the block: read psi (and the
-// neighbour's link for -mu hops) from memory and accumulate into q
-template <int MU, typename S, typename A>
+// Hops of site s whose neighbour lies outside the block: read psi (and the
+// neighbour's link for -mu hops) from memory and accumulate into q.  One hop
+// per loop trip.
+template <typename S, typename A, bool REGLINKS>
 __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
                                           const vec2_t<S> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
-                                          const cx<A> U[9], cx<A> q[12])
+                                          const cx<A> Ur[REGLINKS ? 4 : 1][9], cx<A> q[12])
 {
-    int bn, sn, sign;
-    bool inb;
-    cx<A> p[12], h[6], t[6];
-    neighbour<MU, +1>(g, b, bc, s, bn, sn, sign, inb);
-    if (!inb) {
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+        int bn, sn, sign;
+        bool inb;
+        neighbour_rt(g, b, bc, s, mu, dir, bn, sn, sign, inb);
+        if (inb) continue;
+        cx<A> p[12], h[6], t[6], U[9];
         const vec2_t<S> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
-        proj_minus<MU>(p, h);
-        su3_mul(U, h, t);
-        recon_minus<MU>(q, t, (A)(-0.5 * sign));
-    }
-    neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
-    if (!inb) {
-        const vec2_t<S> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
+        const A kk = (A)(sign > 0 ? -0.5f : 0.5f);
+        if (dir > 0) {
+            if (REGLINKS) {
+                // explicit branches: a switch would become a dynamic register index
+                if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
+                else if (mu == 1) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 1 : 0][e]; }
+                else if (mu == 2) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 2 : 0][e]; }
+                else { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 3 : 0][e]; }
+            } else {
+                get_link<false, S, A>(Ur, links, b, s, mu, U);
+            }
+            proj_m(mu, p, h);
+            su3_mul(U, h, t);
+            recon_m(mu, q, t, kk);
+        } else {
+            const vec2_t<S> *u = links + ((long)bn * 4 + mu) * 9 * BS + sn;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
-        cx<A> Un[9];
-        const vec2_t<S> *u = links + ((long)bn * 4 + MU) * 9 * BS + sn;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) Un[e] = ldc<A>(u + e * BS);
-        proj_plus<MU>(p, h);
-        su3_mul_adj(Un, h, t);
-        recon_plus<MU>(q, t, (A)(-0.5 * sign));
+            for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+            proj_p(mu, p, h);
+            su3_mul_adj(U, h, t);
+            recon_p(mu, q, t, kk);
+        }
     }
 }
 
@@ -139,11 +268,12 @@ template <typename A> __device__ __forceinline__ A wave_sum(A v)
     return v;
 }
 
-template <typename S, typename A, bool REGCLOV>
-__global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ eta, vec2_t<S> *__restrict__ psi,
-                                                  const vec2_t<S> *__restrict__ links,
-                                                  const vec2_t<S> *__restrict__ clov, SArgs a)
+template <typename S, typename A, typename RES>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
+    const vec2_t<S> *__restrict__ eta, vec2_t<S> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
+    const vec2_t<S> *__restrict__ clov, SArgs a)
 {
+    constexpr bool REGCLOV = RES::clover, REGLINKS = RES::links;
     __shared__ Lds<A> L;
     const int i = xcd_remap(blockIdx.x, gridDim.x);
     const int b = a.blocks[i];
@@ -152,12 +282,14 @@ __global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ 
     int bc[4];
     block_coords(a.g, b, bc);
 
-    cx<A> U[4][9];
+    cx<A> U[REGLINKS ? 4 : 1][9];
+    if (REGLINKS) {
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
+        for (int mu = 0; mu < (REGLINKS ? 4 : 1); ++mu) {
+            const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) U[mu][e] = ldc<A>(u + e * BS);
+            for (int e = 0; e < 9; ++e) U[mu][e] = ldc<A>(u + e * BS);
+        }
     }
     cx<A> cl[REGCLOV ? 36 : 1];
     if (REGCLOV) {
@@ -182,21 +314,18 @@ __global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ 
         if (a.mode != 0) {
             // rho = eta - (D psi)_B ; psi_B is held in del
             if (a.mode == 2) {
-                block_apply<S, A, REGCLOV>(L, a.g, b, bc, s, U, cl, clov, diag, del, q);
+                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, del, q);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
             }
-            face_hops<0, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[0], q);
-            face_hops<1, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[1], q);
-            face_hops<2, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[2], q);
-            face_hops<3, S, A>(a.g, b, bc, s, r, a.nrhs, psi, links, U[3], q);
+            face_hops<S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) rr[c] = rr[c] - q[c];
         }
         // MR on D_BB: del accumulates alpha * r on top of psi_B
         for (int it = 0; it < a.nmr; ++it) {
-            block_apply<S, A, REGCLOV>(L, a.g, b, bc, s, U, cl, clov, diag, rr, q);
+            block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
             A qr_re = 0, qr_im = 0, qq = 0;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -232,7 +361,7 @@ __global__ __launch_bounds__(BS) void k_sap_sweep(const vec2_t<S> *__restrict__ 
     }
 }
 
-template <typename S, typename A, bool REGCLOV>
+template <typename S, typename A, typename RES>
 Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 {
     // algorithmic traffic of one colour sweep: links + clover once, eta, psi
@@ -241,12 +370,20 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
     const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0)));
     const double fl = sites * n * (a.nmr * 2184.0 + (a.mode == 2 ? 1848.0 : 0.0));
     ProfScope ps(ctx->prof, ctx->stream, prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16, by, fl);
-    k_sap_sweep<S, A, REGCLOV><<<a.nblk, BS, 0, ctx->stream>>>(
+    k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
         static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
         static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p), a);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
+
+// Chosen by measurement on MI355X (32^3x64 colour sweep, single RHS):
+// links in registers and the clover re-read from L2 per block application
+// beat both "everything in registers" (one workgroup per CU, register
+// pressure) and "everything from L2".
+typedef Residency<true, false, 2> ResF32;
+typedef Residency<true, false, 1> ResF16;
+typedef Residency<true, false, 1> ResF64;
 
 } // namespace
 
@@ -274,9 +411,9 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
             a.blocks = ctx->colour_blocks[col].as<int>();
             a.nblk = ctx->ncolour[col];
             a.mode = (cy == 0 && col == 0) ? 0 : (cy == 0 ? 1 : 2);
-            if (prec == DD_F64) DD_TRY((sweep<double, double, false>(ctx, a, prec, eta, psi)));
-            else if (prec == DD_F32) DD_TRY((sweep<float, float, true>(ctx, a, prec, eta, psi)));
-            else DD_TRY((sweep<__half, float, true>(ctx, a, prec, eta, psi)));
+            if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64>(ctx, a, prec, eta, psi)));
+            else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32>(ctx, a, prec, eta, psi)));
+            else DD_TRY((sweep<__half, float, ResF16>(ctx, a, prec, eta, psi)));
         }
     return Status::ok();
 }

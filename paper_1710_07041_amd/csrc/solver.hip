@@ -82,16 +82,20 @@ __global__ __launch_bounds__(TPB) void k_dots(const double2 *__restrict__ V, lon
 {
     __shared__ double red[4];
     const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
-    C64 acc[NV];
+    C64 acc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = mk(0.0, 0.0);
     for (int b = g; b < nblocks; b += G) {
         const long base = ((long)b * nrhs + r) * 12 * BS + s;
         for (int c = 0; c < 12; ++c) {
             C64 wc = ldc<double>(w + base + c * BS);
+            // unconditional loads keep all NV in flight; slots i >= nv
+            // re-read the last vector and are never written out
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) cmacc(acc[i], ldc<double>(V + i * vstride + base + c * BS), wc);
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : nv - 1;
+                cmacc(acc[i], ldc<double>(V + ii * vstride + base + c * BS), wc);
+            }
         }
     }
 #pragma unroll
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(TPB) void k_update_dots(const double2 *__restrict__
 {
     __shared__ double red[4];
     const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
-    C64 hc[NV], acc[NV];
+    C64 hc[NV > 0 ? NV : 1], acc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         acc[i] = mk(0.0, 0.0);
@@ -124,18 +128,17 @@ __global__ __launch_bounds__(TPB) void k_update_dots(const double2 *__restrict__
     for (int b = g; b < nblocks; b += G) {
         const long base = ((long)b * nrhs + r) * 12 * BS + s;
         for (int c = 0; c < 12; ++c) {
-            C64 vv[NV];
+            C64 vv[NV > 0 ? NV : 1];
             C64 wc = ldc<double>(w + base + c * BS);
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) {
-                    vv[i] = ldc<double>(V + i * vstride + base + c * BS);
-                    wc = wc - hc[i] * vv[i];
-                }
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : nv - 1; // hc[i] = 0 beyond nv
+                vv[i] = ldc<double>(V + ii * vstride + base + c * BS);
+                wc = wc - hc[i] * vv[i];
+            }
             stc(w + base + c * BS, wc);
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) cmacc(acc[i], vv[i], wc);
+            for (int i = 0; i < NV; ++i) cmacc(acc[i], vv[i], wc);
             n2 = fma(wc.re, wc.re, fma(wc.im, wc.im, n2));
             mx = fmax(mx, fmax(fabs(wc.re), fabs(wc.im)));
         }
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restr
     const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
     NormInfo ni = norm_info(res, K, nv, r, active, fp16_scale != 0);
     if (g == 0 && s == 0 && scl) scl[r] = ni.scale;
-    C64 hc[NV];
+    C64 hc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) hc[i] = i < nv ? ldc<double>(res + (long)r * K + i) : mk(0.0, 0.0);
     for (int b = g; b < nblocks; b += G) {
@@ -199,8 +202,10 @@ __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restr
         for (int c = 0; c < 12; ++c) {
             C64 wc = ldc<double>(w + base + c * BS);
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) wc = wc - hc[i] * ldc<double>(V + i * vstride + base + c * BS);
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : nv - 1; // hc[i] = 0 beyond nv
+                wc = wc - hc[i] * ldc<double>(V + ii * vstride + base + c * BS);
+            }
             C64 v = ni.inv * wc;
             stc(vnext + base + c * BS, v);
             if (lp) stc(lp + base + c * BS, ni.scale * v);
@@ -240,7 +245,8 @@ __global__ __launch_bounds__(TPB) void k_combine(double2 *__restrict__ x, const 
     // columns beyond this right-hand side's cycle length are never read (a
     // dropped column may hold non-finite values)
     nv = nv < len[r] ? nv : len[r];
-    C64 yc[NV];
+    if (nv == 0) return;
+    C64 yc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) yc[i] = i < nv ? ldc<double>(y + (long)r * MAXM + i) : mk(0.0, 0.0);
     for (int b = g; b < nblocks; b += G) {
@@ -248,8 +254,10 @@ __global__ __launch_bounds__(TPB) void k_combine(double2 *__restrict__ x, const 
         for (int c = 0; c < 12; ++c) {
             C64 xc = ldc<double>(x + base + c * BS);
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) cmac(xc, yc[i], ldc<double>(Z + i * zstride + base + c * BS));
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : nv - 1; // yc[i] = 0 beyond nv
+                cmac(xc, yc[i], ldc<double>(Z + ii * zstride + base + c * BS));
+            }
             stc(x + base + c * BS, xc);
         }
     }
@@ -299,12 +307,9 @@ namespace {
 
 int pick_bucket(int nv)
 {
-    if (nv <= 1) return 1;
-    if (nv <= 4) return 4;
-    if (nv <= 8) return 8;
-    if (nv <= 12) return 12;
-    if (nv <= 16) return 16;
-    if (nv <= 22) return 22;
+    static const int b[] = {0, 1, 2, 3, 4, 6, 8, 10, 12, 14, 16, 18, 20, 22, 24, 28, 33};
+    for (int v : b)
+        if (nv <= v) return v;
     return 33;
 }
 
@@ -314,7 +319,7 @@ struct Launch {
     dim3 grid() const { return dim3(W->G, W->nrhs); }
 };
 
-#define DD_BUCKETS(X) X(1) X(4) X(8) X(12) X(16) X(22) X(33)
+#define DD_BUCKETS(X) X(0) X(1) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(28) X(33)
 
 double vec64_bytes(const Launch &L) { return (double)L.W->vlen * 16.0; }
 
