@@ -109,9 +109,9 @@ struct ProfScope {
     ~ProfScope();
 };
 
-struct SolverWork; // solver.hip
-struct SolverWorkDeleter {
-    void operator()(SolverWork *w) const; // solver.hip
+class Engine; // engine.hip
+struct EngineDeleter {
+    void operator()(Engine *e) const; // engine.hip
 };
 
 } // namespace dd
@@ -128,7 +128,7 @@ struct dd_ctx {
     int ncolour[2] = {0, 0};
     std::string err;
     dd::Prof prof;
-    std::unique_ptr<dd::SolverWork, dd::SolverWorkDeleter> work;
+    std::unique_ptr<dd::Engine, dd::EngineDeleter> engine; // reused by dd_solve
 };
 
 namespace dd {
@@ -141,21 +141,34 @@ Status build_fields(dd_ctx *ctx, const double *U_dev_canon, double csw);
 Status set_clover_canon(dd_ctx *ctx, const double *C_dev_canon);
 Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs);
 Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs);
+// one FP64 right-hand side <-> slot `slot` of a `width`-wide blocked FP64 buffer
+Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot);
+Status unpack_slot(dd_ctx *ctx, hipStream_t st, const void *blocked, double *canon, int width, int slot);
 Status any_nonfinite(dd_ctx *ctx, const double *p, size_t n, bool &bad);
 
 // dslash.hip
 // out = D in (resid == nullptr) or out = resid - D in.  in_prec may differ
-// from out_prec only for (F32 in, F64 out) and (F64 in, F64 out).
+// from out_prec only for (F32 in, F64 out) and (F64 in, F64 out).  Masses
+// come from the host array m0 or, when m0_dev is set, from device memory;
+// in_off (device, nullable) adds a per-rhs element offset to the input.
 Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
-                     int field_prec, const double *resid);
+                     int field_prec, const double *resid, const double *m0_dev = nullptr,
+                     const long *in_off = nullptr);
 Status launch_dslash_block(dd_ctx *ctx, double m0, int block_id, const void *in, void *out, int prec);
 
 // sap.hip
-Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec);
+// Per-slot device data for batched use: masses and element offsets of each
+// right-hand side's eta and psi chunks (all device pointers, nullable).
+struct SapSlots {
+    const double *m0_dev = nullptr;
+    const long *eta_off = nullptr;
+    const long *psi_off = nullptr;
+};
+Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
+               const SapSlots *slots = nullptr);
 
-// solver.hip
+// engine.hip
 Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,
              dd_solve_info *info);
-void free_solver_work(dd_ctx *ctx);
 
 } // namespace dd

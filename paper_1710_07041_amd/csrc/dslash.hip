@@ -21,6 +21,8 @@ struct DArgs {
     int nrhs;
     int block_id;
     double m0[MAXRHS];
+    const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
+    const long *in_off;   // per-rhs element offset added to the input (nullable)
 };
 
 // The eight hops run as a loop that is deliberately not unrolled: unrolled,
@@ -81,12 +83,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
     const int s = threadIdx.x;
     int bc[4];
     block_coords(a.g, b, bc);
+    if (a.in_off) in += a.in_off[r];
     cx<A> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mk<A>(0, 0);
     hops<BLOCKONLY, SI, SF, A>(in, links, a, b, bc, r, s, acc);
     const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
-    const A diag = (A)(4.0 + a.m0[r]);
+    const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
@@ -118,7 +121,7 @@ DArgs make_args(const dd_ctx *ctx, const double *m0, int nrhs)
     }
     a.g.nblocks = ctx->g.nblocks;
     a.nrhs = nrhs;
-    for (int r = 0; r < nrhs && r < MAXRHS; ++r) a.m0[r] = m0[r];
+    for (int r = 0; r < nrhs && r < MAXRHS && m0; ++r) a.m0[r] = m0[r];
     return a;
 }
 
@@ -142,11 +145,13 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
 } // namespace
 
 Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
-                     int field_prec, const double *resid)
+                     int field_prec, const double *resid, const double *m0_dev, const long *in_off)
 {
-    if (!in || !out || !ctx->links[field_prec].p || !ctx->clover[field_prec].p)
+    if (!in || !out || !ctx->links[field_prec].p || !ctx->clover[field_prec].p || (!m0 && !m0_dev))
         return Status{DD_INVALID_ARG, "operator: missing buffer"};
     DArgs a = make_args(ctx, m0, nrhs);
+    a.m0_dev = m0_dev;
+    a.in_off = in_off;
     bool rs = resid != nullptr;
     if (in_prec == DD_F64 && out_prec == DD_F64 && field_prec == DD_F64)
         return rs ? launch<double, double, double, double, true>(ctx, a, in, out, DD_F64, resid)

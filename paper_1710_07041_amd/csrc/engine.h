@@ -1,0 +1,73 @@
+// Batched SAP-preconditioned FGMRES engine with independent slots (engine.hip).
+#pragma once
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+constexpr int ENGINE_MAXW = 16; // slots per engine (right-hand sides fused per launch)
+constexpr int ENGINE_MAXM = 32; // largest Krylov dimension
+
+struct EngineParams {
+    int width = 1;
+    int m = 20;
+    int ncy = 4;
+    int nmr = 4;
+    int sap_prec = DD_F32;
+    double tol = 1e-10;
+    int max_restarts = 100;
+    bool graphs = false; // capture the Arnoldi step as hipGraphs (needs a non-null stream)
+};
+
+enum SlotStateKind { SLOT_FREE = 0, SLOT_RESTART = 1, SLOT_CYCLE = 2, SLOT_DONE = 3 };
+
+struct SlotState {
+    int state = SLOT_FREE;
+    int j = 0;         // Arnoldi steps in the current cycle
+    int cycle_len = 0; // length of a cycle that just ended (combine pending)
+    bool need_bnorm = false;
+    double bnorm = 0, m0 = 0;
+    std::vector<std::complex<double>> H, g, sn;
+    std::vector<double> cs;
+    dd_solve_info info{};
+    long owner = 0; // caller's tag (request id) and right-hand-side index
+    int owner_rhs = 0;
+};
+
+class Engine {
+  public:
+    Engine();
+    ~Engine();
+    Status init(dd_ctx *ctx, const EngineParams &p);
+    void set_params(const EngineParams &p);
+    // Place right-hand side b (canonical FP64, device) with initial guess x0
+    // (canonical FP64 device, or nullptr for zero) into free slot r.
+    Status admit(int r, const double *b_canon, const double *x0_canon, double m0, long owner, int owner_rhs);
+    // One restart phase then one Arnoldi step for every busy slot (synchronises).
+    Status iterate();
+    // The same, split so that several engines can overlap on the device.
+    Status launch_restart();
+    Status finish_restart();
+    Status launch_step();
+    Status finish_step();
+    // Copy slot r's solution to a canonical FP64 device buffer (async).
+    Status extract(int r, double *x_canon);
+    void release(int r);
+    int free_slot() const;
+    int busy_slots() const;
+    int width() const;
+    const EngineParams &params() const;
+    SlotState &slot(int r);
+    dd_ctx *ctx() const;
+    static size_t bytes_per_slot(const GeomHost &g, int m, int sap_prec);
+
+  private:
+    struct Impl;
+    std::unique_ptr<Impl> d;
+};
+
+} // namespace dd

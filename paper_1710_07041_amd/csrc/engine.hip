@@ -1,0 +1,958 @@
+// Batched SAP-preconditioned FGMRES engine with independent slots.
+//
+// Flexible GMRES (Saad, SIAM J. Sci. Comput. 14 (1993) 461) with an FP64
+// outer iteration and the red-black Schwarz smoother in FP64, FP32 or FP16
+// storage -- the mixed-precision structure of the paper's solver (Sec. 3.1:
+// mixed precision, some data structures in half precision; the Schwarz method
+// as the fine-grid smoother).  Flexible GMRES is needed because SAP with MR
+// block solves is not a linear map of its input.
+//
+// One engine serves `width` right-hand-side slots of one lattice.  Every slot
+// runs its own FGMRES(m): its own mass, restart count, Arnoldi index j and
+// Hessenberg matrix.  The device work of one Arnoldi step is fused over all
+// slots that are inside a cycle:
+//   z_j   = SAP(v_j)          (one multi-RHS SAP launch per colour sweep; the
+//                              smoother writes straight into slot r's Z[j_r])
+//   w     = D z_j             (FP64 operator reading the stored z_j, so the
+//                              Arnoldi relation D Z = V H holds exactly)
+//   CGS2  in three fused passes over V, each slot with its own j_r:
+//     (1) h1 = V^+ w
+//     (2) w' = w - V h1, h2 = V^+ w', |w'|^2, max|w'|
+//     (3) w'' = w' - V h2, v_{j+1} = w''/h, smoother-precision copy,
+//         h^2 = |w'|^2 - |h2|^2
+// Per-slot data (masses, basis indices, masks, offsets) live in device
+// memory, so the launch sequence of a step has fixed arguments and is
+// captured once per CGS bucket as a hipGraph and replayed.  Reductions are
+// two-stage with a fixed summation order; one small device-to-host copy per
+// phase feeds the host-side Givens rotations and stopping tests.  Restarts
+// recompute the true residual b - D x in FP64; a slot stops only on it.
+//
+// A slot whose cycle ends early rides along in the fused launches until its
+// restart: its masked writes are skipped and its columns are never read.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstddef>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "dd_device.h"
+#include "dd_internal.h"
+#include "engine.h"
+
+namespace dd {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int KMAX = ENGINE_MAXM + 3;  // reduction slots per rhs
+constexpr int K_NORM = KMAX - 2;       // |w|^2
+constexpr int K_MAX = KMAX - 1;        // max|w|
+typedef cx<double> C64;
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+// workgroup sum / max in a fixed order (result valid in every thread)
+__device__ __forceinline__ double wg_sum(double v, double *red)
+{
+    v = wave_sum_d(v);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return ((red[0] + red[1]) + red[2]) + red[3];
+}
+__device__ __forceinline__ double wg_max(double v, double *red)
+{
+    v = wave_max_d(v);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__device__ __forceinline__ int slot_nv(const int *nv_dev, int nvmax, int r) { return nv_dev ? nv_dev[r] : nvmax; }
+
+// Pass 1: partial[g][r][i] = this workgroup's share of <V_i, w>, i < nv_r.
+template <int NV>
+__global__ __launch_bounds__(TPB) void k_dots(const double2 *__restrict__ V, long vstride, int nvmax,
+                                              const int *__restrict__ nv_dev, const double2 *__restrict__ w,
+                                              double2 *__restrict__ partial, int nblocks, int nrhs)
+{
+    __shared__ double red[4];
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    const int nv = slot_nv(nv_dev, nvmax, r);
+    C64 acc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = mk(0.0, 0.0);
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            C64 wc = ldc<double>(w + base + c * BS);
+            // unconditional loads keep all NV in flight; slots i >= nv
+            // re-read a valid vector and are never used
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0);
+                cmacc(acc[i], ldc<double>(V + ii * vstride + base + c * BS), wc);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < nv) { // uniform over the workgroup
+            double re = wg_sum(acc[i].re, red);
+            double im = wg_sum(acc[i].im, red);
+            if (s == 0) partial[((long)g * nrhs + r) * KMAX + i] = make_double2(re, im);
+        }
+    }
+}
+
+// Pass 2: w' = w - sum_{i<nv_r} h[r][i] V_i ; partial <V_i, w'>, |w'|^2, max|w'|.
+template <int NV>
+__global__ __launch_bounds__(TPB) void k_update_dots(const double2 *__restrict__ V, long vstride, int nvmax,
+                                                     const int *__restrict__ nv_dev, const double2 *__restrict__ h,
+                                                     double2 *__restrict__ w, double2 *__restrict__ partial,
+                                                     int nblocks, int nrhs)
+{
+    __shared__ double red[4];
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    const int nv = slot_nv(nv_dev, nvmax, r);
+    C64 hc[NV > 0 ? NV : 1], acc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        acc[i] = mk(0.0, 0.0);
+        hc[i] = i < nv ? ldc<double>(h + (long)r * KMAX + i) : mk(0.0, 0.0);
+    }
+    double n2 = 0.0, mx = 0.0;
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            C64 vv[NV > 0 ? NV : 1];
+            C64 wc = ldc<double>(w + base + c * BS);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0); // hc[i] = 0 beyond nv
+                vv[i] = ldc<double>(V + ii * vstride + base + c * BS);
+                wc = wc - hc[i] * vv[i];
+            }
+            if (NV > 0) stc(w + base + c * BS, wc);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) cmacc(acc[i], vv[i], wc);
+            n2 = fma(wc.re, wc.re, fma(wc.im, wc.im, n2));
+            mx = fmax(mx, fmax(fabs(wc.re), fabs(wc.im)));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < nv) {
+            double re = wg_sum(acc[i].re, red);
+            double im = wg_sum(acc[i].im, red);
+            if (s == 0) partial[((long)g * nrhs + r) * KMAX + i] = make_double2(re, im);
+        }
+    }
+    double tn = wg_sum(n2, red);
+    double tm = wg_max(mx, red);
+    if (s == 0) {
+        partial[((long)g * nrhs + r) * KMAX + K_NORM] = make_double2(tn, 0.0);
+        partial[((long)g * nrhs + r) * KMAX + K_MAX] = make_double2(tm, 0.0);
+    }
+}
+
+// Normalisation constants of slot r from the reduced pass-2 results.
+struct NormInfo {
+    double inv;   // 1/h (0 when h == 0)
+    double scale; // factor applied to the smoother-precision copy
+};
+__device__ __forceinline__ NormInfo norm_info(const double2 *res, int nv, int r, bool fp16_scale)
+{
+    NormInfo ni{0.0, 0.0};
+    const double2 *row = res + (long)r * KMAX;
+    double h2 = row[K_NORM].x;
+    for (int i = 0; i < nv; ++i) h2 -= row[i].x * row[i].x + row[i].y * row[i].y;
+    double hn = sqrt(fmax(h2, 0.0));
+    if (hn == 0.0) return ni;
+    ni.inv = 1.0 / hn;
+    // max|v| <= (max|w'| + a correction of the size of |h2|) / h; 1.0625 is head room
+    double mxv = row[K_MAX].x * ni.inv * 1.0625;
+    ni.scale = fp16_scale ? (mxv > 0.0 ? 1.0 / mxv : 1.0) : 1.0;
+    return ni;
+}
+
+// Pass 3: w'' = w' - sum_{i<nv_r} h2[r][i] V_i ; V[dst_r] = w''/h ; lp = scale * V[dst_r].
+// Slots with active[r] == 0 write nothing.
+template <int NV, typename SL>
+__global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restrict__ V, long vstride, int nvmax,
+                                                          const int *__restrict__ nv_dev,
+                                                          const int *__restrict__ dst_dev,
+                                                          const double2 *__restrict__ res,
+                                                          const double2 *__restrict__ w, double2 *__restrict__ Vout,
+                                                          vec2_t<SL> *__restrict__ lp, double *__restrict__ scl,
+                                                          const int *__restrict__ active, int fp16_scale,
+                                                          int nblocks, int nrhs)
+{
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const int nv = slot_nv(nv_dev, nvmax, r);
+    const int dst = dst_dev ? dst_dev[r] : nvmax;
+    NormInfo ni = norm_info(res, nv, r, fp16_scale != 0);
+    if (g == 0 && s == 0 && scl) scl[r] = ni.scale;
+    C64 hc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hc[i] = i < nv ? ldc<double>(res + (long)r * KMAX + i) : mk(0.0, 0.0);
+    double2 *vnext = Vout + dst * vstride;
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            C64 wc = ldc<double>(w + base + c * BS);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0);
+                wc = wc - hc[i] * ldc<double>(V + ii * vstride + base + c * BS);
+            }
+            C64 v = ni.inv * wc;
+            stc(vnext + base + c * BS, v);
+            if (lp) stc(lp + base + c * BS, ni.scale * v);
+        }
+    }
+}
+
+// Second stage of every reduction: out[r][k] = sum_g partial[g][r][k]
+// (slot K_MAX takes the maximum); fixed order.
+__global__ __launch_bounds__(TPB) void k_reduce(const double2 *__restrict__ partial, double2 *__restrict__ out, int G,
+                                                int nrhs)
+{
+    __shared__ double red[4];
+    const int r = blockIdx.y, k = blockIdx.x, s = threadIdx.x;
+    const bool is_max = (k == K_MAX);
+    double re = 0.0, im = 0.0;
+    for (int g = s; g < G; g += TPB) {
+        double2 v = partial[((long)g * nrhs + r) * KMAX + k];
+        if (is_max) re = fmax(re, v.x);
+        else {
+            re += v.x;
+            im += v.y;
+        }
+    }
+    double tre = is_max ? wg_max(re, red) : wg_sum(re, red);
+    double tim = is_max ? 0.0 : wg_sum(im, red);
+    if (s == 0) out[(long)r * KMAX + k] = make_double2(tre, tim);
+}
+
+// x_r += sum_{i < len_r} y[r][i] Z_i  (Z in FP64 or FP32)
+template <int NV, typename SZ>
+__global__ __launch_bounds__(TPB) void k_combine(double2 *__restrict__ x, const vec2_t<SZ> *__restrict__ Z, long zstride,
+                                                 int nvmax, const double2 *__restrict__ y, const int *__restrict__ len,
+                                                 int nblocks, int nrhs)
+{
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    const int nv = nvmax < len[r] ? nvmax : len[r];
+    if (nv <= 0) return;
+    C64 yc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) yc[i] = i < nv ? ldc<double>(y + (long)r * ENGINE_MAXM + i) : mk(0.0, 0.0);
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            C64 xc = ldc<double>(x + base + c * BS);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < nv ? i : nv - 1; // yc[i] = 0 beyond nv
+                cmac(xc, yc[i], ldc<double>(Z + ii * zstride + base + c * BS));
+            }
+            stc(x + base + c * BS, xc);
+        }
+    }
+}
+
+// FP16 smoother output -> FP32 basis vector: Z[off_r] = out / scale_r
+__global__ __launch_bounds__(TPB) void k_unscale(const __half2 *__restrict__ in, float2 *__restrict__ Z,
+                                                 const long *__restrict__ zoff, const double *__restrict__ scl,
+                                                 const int *__restrict__ active, int nblocks, int nrhs)
+{
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const double sc = scl[r];
+    const float f = sc != 0.0 ? (float)(1.0 / sc) : 0.0f;
+    float2 *out = Z + zoff[r];
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) stc(out + base + c * BS, f * ldc<float>(in + base + c * BS));
+    }
+}
+
+// out_r[out_off_r] = in_r[in_off_r] for active slots (identity preconditioner)
+template <typename S>
+__global__ __launch_bounds__(TPB) void k_slot_copy(const vec2_t<S> *__restrict__ in, const long *__restrict__ in_off,
+                                                   vec2_t<S> *__restrict__ out, const long *__restrict__ out_off,
+                                                   const int *__restrict__ active, int nblocks, int nrhs)
+{
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const vec2_t<S> *src = in + (in_off ? in_off[r] : 0);
+    vec2_t<S> *dst = out + (out_off ? out_off[r] : 0);
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) dst[base + c * BS] = src[base + c * BS];
+    }
+}
+
+int pick_bucket(int nv)
+{
+    static const int b[] = {0, 1, 2, 3, 4, 6, 8, 10, 12, 14, 16, 18, 20, 22, 24, 28, 33};
+    for (int v : b)
+        if (nv <= v) return v;
+    return 33;
+}
+#define DD_BUCKETS(X) X(0) X(1) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(28) X(33)
+
+typedef std::complex<double> Z64;
+
+// LAPACK zlartg semantics: [c s; -conj(s) c] [f; g] = [r; 0], c >= 0 real
+void givens(Z64 f, Z64 g, double &c, Z64 &s, Z64 &r)
+{
+    double af = std::abs(f), ag = std::abs(g);
+    if (ag == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        r = f;
+    } else if (af == 0.0) {
+        c = 0.0;
+        s = std::conj(g) / ag;
+        r = ag;
+    } else {
+        double nrm = std::hypot(af, ag);
+        Z64 ph = f / af;
+        c = af / nrm;
+        s = ph * std::conj(g) / nrm;
+        r = ph * nrm;
+    }
+}
+
+} // namespace
+
+// per-slot arrays shared by host (pinned) and device, one upload per phase
+struct SlotArrays {
+    int active[ENGINE_MAXW];
+    int nv[ENGINE_MAXW];
+    int dst[ENGINE_MAXW];
+    int len[ENGINE_MAXW];
+    double m0[ENGINE_MAXW];
+    long eta_off[ENGINE_MAXW];
+    long psi_off[ENGINE_MAXW];
+    long in_off[ENGINE_MAXW];
+};
+
+struct Engine::Impl {
+    dd_ctx *ctx = nullptr;
+    EngineParams P{};
+    int W = 0;
+    int zprec = DD_F32;
+    int sap_prec = DD_F32;
+    long vlen = 0; // complex entries of one width-wide vector
+    int G = 0;
+    DevBuf V, Z, w, xb, bb, lp, sapout, partial, res, res2, resb, y, scl, slots;
+    SlotArrays *h_slots[3] = {nullptr, nullptr, nullptr}; // ring of pinned staging buffers
+    int ring = 0;
+    double2 *h_res = nullptr, *h_res2 = nullptr, *h_resb = nullptr, *h_y = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<SlotState> S;
+    std::map<int, hipGraphExec_t> graphs;
+    bool restart_pending = false, step_pending = false, bnorm_pending = false;
+
+    ~Impl()
+    {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto p : h_slots)
+            if (p) (void)hipHostFree(p);
+        if (h_res) (void)hipHostFree(h_res);
+        if (h_res2) (void)hipHostFree(h_res2);
+        if (h_resb) (void)hipHostFree(h_resb);
+        if (h_y) (void)hipHostFree(h_y);
+        if (ev) (void)hipEventDestroy(ev);
+    }
+
+    hipStream_t st() const { return ctx->stream; }
+    dim3 grid() const { return dim3(G, W); }
+    SlotArrays *dev_slots() const { return slots.as<SlotArrays>(); }
+    const int *d_active() const { return dev_slots()->active; }
+    const int *d_nv() const { return dev_slots()->nv; }
+    const int *d_dst() const { return dev_slots()->dst; }
+    const int *d_len() const { return dev_slots()->len; }
+    const double *d_m0() const { return dev_slots()->m0; }
+    const long *d_eta_off() const { return dev_slots()->eta_off; }
+    const long *d_psi_off() const { return dev_slots()->psi_off; }
+    const long *d_in_off() const { return dev_slots()->in_off; }
+    double vec64() const { return (double)vlen * 16.0; }
+
+    SlotArrays &stage()
+    {
+        ring = (ring + 1) % 3;
+        return *h_slots[ring];
+    }
+    Status upload(const SlotArrays &h)
+    {
+        DD_HIP_TRY(hipMemcpyAsync(slots.p, &h, sizeof(SlotArrays), hipMemcpyHostToDevice, st()));
+        return Status::ok();
+    }
+    void fill_common(SlotArrays &h)
+    {
+        for (int r = 0; r < ENGINE_MAXW; ++r) {
+            h.m0[r] = r < W ? S[r].m0 : 0.0;
+            h.len[r] = 0;
+        }
+    }
+
+    // ---- launch helpers -------------------------------------------------
+    Status dots(const double2 *w, int nvmax)
+    {
+        ProfScope ps(ctx->prof, st(), K_CGS_DOTS, vec64() * (nvmax + 1), 8.0 * vlen * nvmax);
+        switch (pick_bucket(nvmax)) {
+#define C(N) case N: k_dots<N><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, N, d_nv(), w, partial.as<double2>(), ctx->g.nblocks, W); break;
+            DD_BUCKETS(C)
+#undef C
+        }
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+    // nvmax == 0: plain |w|^2 and max|w| (no vectors, w untouched)
+    Status update_dots(double2 *wv, int nvmax, const double2 *h)
+    {
+        ProfScope ps(ctx->prof, st(), K_CGS_UPDATE, vec64() * (nvmax + (nvmax > 0 ? 2 : 1)),
+                     16.0 * vlen * nvmax + 4.0 * vlen);
+        const int *nvp = nvmax > 0 ? d_nv() : nullptr;
+        switch (pick_bucket(nvmax)) {
+#define C(N) case N: k_update_dots<N><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, nvmax == 0 ? 0 : N, nvp, h, wv, partial.as<double2>(), ctx->g.nblocks, W); break;
+            DD_BUCKETS(C)
+#undef C
+        }
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+    template <typename SL> Status normalize_t(int nvmax, const double2 *r2, const double2 *wv, void *lpp, bool fp16)
+    {
+        ProfScope ps(ctx->prof, st(), K_CGS_NORMALIZE, vec64() * (nvmax + 2) + (lpp ? (double)vlen * 2 * sizeof(SL) : 0.0),
+                     8.0 * vlen * (nvmax + 1));
+        const int *nvp = nvmax > 0 ? d_nv() : nullptr;
+        switch (pick_bucket(nvmax)) {
+#define C(N) case N: k_update_normalize<N, SL><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, nvmax == 0 ? 0 : N, nvp, d_dst(), r2, wv, V.as<double2>(), static_cast<vec2_t<SL> *>(lpp), scl.as<double>(), d_active(), fp16 ? 1 : 0, ctx->g.nblocks, W); break;
+            DD_BUCKETS(C)
+#undef C
+        }
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+    Status normalize(int nvmax, const double2 *r2, const double2 *wv)
+    {
+        if (sap_prec == DD_F64) return normalize_t<double>(nvmax, r2, wv, nullptr, false);
+        if (sap_prec == DD_F32) return normalize_t<float>(nvmax, r2, wv, lp.p, false);
+        return normalize_t<__half>(nvmax, r2, wv, lp.p, true);
+    }
+    Status reduce(double2 *out)
+    {
+        ProfScope ps(ctx->prof, st(), K_REDUCE, (double)G * W * KMAX * 16.0, 0.0);
+        k_reduce<<<dim3(KMAX, W), TPB, 0, st()>>>(partial.as<double2>(), out, G, W);
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+    Status combine(int nvmax)
+    {
+        ProfScope ps(ctx->prof, st(), K_COMBINE, vec64() * 2 + (double)vlen * 2 * real_bytes(zprec) * nvmax,
+                     8.0 * vlen * nvmax);
+        const double2 *yp = y.as<double2>();
+        if (zprec == DD_F64) {
+            switch (pick_bucket(nvmax)) {
+#define C(N) case N: k_combine<N, double><<<grid(), TPB, 0, st()>>>(xb.as<double2>(), Z.as<double2>(), vlen, nvmax, yp, d_len(), ctx->g.nblocks, W); break;
+                DD_BUCKETS(C)
+#undef C
+            }
+        } else {
+            switch (pick_bucket(nvmax)) {
+#define C(N) case N: k_combine<N, float><<<grid(), TPB, 0, st()>>>(xb.as<double2>(), Z.as<float2>(), vlen, nvmax, yp, d_len(), ctx->g.nblocks, W); break;
+                DD_BUCKETS(C)
+#undef C
+            }
+        }
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+
+    // The fixed launch sequence of one Arnoldi step (captured into a graph).
+    Status step_sequence(int nvmax)
+    {
+        SapSlots ss;
+        ss.m0_dev = d_m0();
+        if (P.ncy == 0) {
+            // no smoother: z_j = v_j (the smoother-precision copy, or V itself in FP64)
+            ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 2 * 2 * real_bytes(zprec), 0.0);
+            if (sap_prec == DD_F64)
+                k_slot_copy<double><<<grid(), TPB, 0, st()>>>(V.as<double2>(), d_eta_off(), Z.as<double2>(), d_psi_off(), d_active(), ctx->g.nblocks, W);
+            else if (sap_prec == DD_F32)
+                k_slot_copy<float><<<grid(), TPB, 0, st()>>>(lp.as<float2>(), nullptr, Z.as<float2>(), d_psi_off(), d_active(), ctx->g.nblocks, W);
+            else
+                k_unscale<<<grid(), TPB, 0, st()>>>(lp.as<__half2>(), Z.as<float2>(), d_psi_off(), scl.as<double>(), d_active(), ctx->g.nblocks, W);
+            DD_HIP_TRY(hipGetLastError());
+        } else if (sap_prec == DD_F64) {
+            ss.eta_off = d_eta_off();
+            ss.psi_off = d_psi_off();
+            DD_TRY(run_sap(ctx, nullptr, W, V.p, Z.p, P.ncy, P.nmr, DD_F64, &ss));
+        } else if (sap_prec == DD_F32) {
+            ss.psi_off = d_psi_off();
+            DD_TRY(run_sap(ctx, nullptr, W, lp.p, Z.p, P.ncy, P.nmr, DD_F32, &ss));
+        } else {
+            DD_TRY(run_sap(ctx, nullptr, W, lp.p, sapout.p, P.ncy, P.nmr, DD_F16, &ss));
+            ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 12.0, 2.0 * vlen);
+            k_unscale<<<grid(), TPB, 0, st()>>>(sapout.as<__half2>(), Z.as<float2>(), d_psi_off(), scl.as<double>(),
+                                                d_active(), ctx->g.nblocks, W);
+            DD_HIP_TRY(hipGetLastError());
+        }
+        DD_TRY(launch_dslash(ctx, nullptr, W, Z.p, zprec, w.p, DD_F64, DD_F64, nullptr, d_m0(), d_in_off()));
+        DD_TRY(dots(w.as<double2>(), nvmax));
+        DD_TRY(reduce(res.as<double2>()));
+        DD_TRY(update_dots(w.as<double2>(), nvmax, res.as<double2>()));
+        DD_TRY(reduce(res2.as<double2>()));
+        DD_TRY(normalize(nvmax, res2.as<double2>(), w.as<double2>()));
+        return Status::ok();
+    }
+};
+
+Engine::Engine() : d(new Impl()) {}
+Engine::~Engine()
+{
+    if (d && d->ctx) (void)hipStreamSynchronize(d->ctx->stream);
+}
+
+size_t Engine::bytes_per_slot(const GeomHost &g, int m, int sap_prec)
+{
+    size_t v = (size_t)g.V * 12 * 16; // one FP64 vector
+    size_t zb = (size_t)g.V * 12 * 2 * real_bytes(sap_prec == DD_F64 ? DD_F64 : DD_F32);
+    size_t lpb = sap_prec == DD_F64 ? 0 : (size_t)g.V * 12 * 2 * real_bytes(DD_F32);
+    size_t so = sap_prec == DD_F16 ? (size_t)g.V * 12 * 4 : 0;
+    return v * (m + 1 + 3) + zb * m + lpb + so;
+}
+
+int Engine::width() const { return d->W; }
+const EngineParams &Engine::params() const { return d->P; }
+SlotState &Engine::slot(int r) { return d->S[r]; }
+dd_ctx *Engine::ctx() const { return d->ctx; }
+
+Status Engine::init(dd_ctx *ctx, const EngineParams &p)
+{
+    Impl &e = *d;
+    if (p.width < 1 || p.width > ENGINE_MAXW || p.m < 1 || p.m > ENGINE_MAXM)
+        return Status{DD_INVALID_ARG, "engine: width or Krylov dimension out of range"};
+    e.ctx = ctx;
+    e.P = p;
+    e.W = p.width;
+    e.sap_prec = p.sap_prec;
+    e.zprec = p.sap_prec == DD_F64 ? DD_F64 : DD_F32;
+    e.vlen = (long)ctx->g.nblocks * e.W * 12 * BS;
+    e.G = ctx->g.nblocks < 1024 ? ctx->g.nblocks : 1024;
+    const size_t v64 = (size_t)e.vlen * 16;
+    DD_TRY(e.V.alloc(v64 * (p.m + 1)));
+    DD_TRY(e.Z.alloc((size_t)e.vlen * 2 * real_bytes(e.zprec) * p.m));
+    DD_TRY(e.w.alloc(v64));
+    DD_TRY(e.xb.alloc(v64));
+    DD_TRY(e.bb.alloc(v64));
+    if (p.sap_prec != DD_F64) DD_TRY(e.lp.alloc((size_t)e.vlen * 2 * real_bytes(DD_F32))); // room for an FP32 fallback
+    if (p.sap_prec == DD_F16) DD_TRY(e.sapout.alloc((size_t)e.vlen * 2 * real_bytes(DD_F16)));
+    DD_TRY(e.partial.alloc((size_t)e.G * e.W * KMAX * 16));
+    DD_TRY(e.res.alloc((size_t)e.W * KMAX * 16));
+    DD_TRY(e.res2.alloc((size_t)e.W * KMAX * 16));
+    DD_TRY(e.resb.alloc((size_t)e.W * KMAX * 16));
+    DD_TRY(e.y.alloc((size_t)e.W * ENGINE_MAXM * 16));
+    DD_TRY(e.scl.alloc((size_t)e.W * 8));
+    DD_TRY(e.slots.alloc(sizeof(SlotArrays)));
+    for (auto &hs : e.h_slots) {
+        DD_HIP_TRY(hipHostMalloc((void **)&hs, sizeof(SlotArrays), hipHostMallocDefault));
+        std::memset(hs, 0, sizeof(SlotArrays));
+    }
+    DD_HIP_TRY(hipHostMalloc((void **)&e.h_res, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
+    DD_HIP_TRY(hipHostMalloc((void **)&e.h_res2, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
+    DD_HIP_TRY(hipHostMalloc((void **)&e.h_resb, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
+    DD_HIP_TRY(hipHostMalloc((void **)&e.h_y, (size_t)e.W * ENGINE_MAXM * 16, hipHostMallocDefault));
+    DD_HIP_TRY(hipEventCreateWithFlags(&e.ev, hipEventDisableTiming));
+    e.S.assign(e.W, SlotState{});
+    for (auto &s : e.S) {
+        s.H.assign((size_t)(p.m + 1) * p.m, 0.0);
+        s.g.assign(p.m + 1, 0.0);
+        s.sn.assign(p.m, 0.0);
+        s.cs.assign(p.m, 0.0);
+    }
+    return Status::ok();
+}
+
+int Engine::free_slot() const
+{
+    for (int r = 0; r < d->W; ++r)
+        if (d->S[r].state == SLOT_FREE) return r;
+    return -1;
+}
+
+int Engine::busy_slots() const
+{
+    int n = 0;
+    for (auto &s : d->S) n += s.state == SLOT_RESTART || s.state == SLOT_CYCLE;
+    return n;
+}
+
+Status Engine::admit(int r, const double *b_canon, const double *x0_canon, double m0, long owner, int owner_rhs)
+{
+    Impl &e = *d;
+    if (r < 0 || r >= e.W || e.S[r].state != SLOT_FREE) return Status{DD_INVALID_ARG, "engine: slot not free"};
+    DD_TRY(pack_slot(e.ctx, e.st(), b_canon, e.bb.p, e.W, r));
+    if (x0_canon) {
+        DD_TRY(pack_slot(e.ctx, e.st(), x0_canon, e.xb.p, e.W, r));
+    } else {
+        // x0 = 0: clear slot r's chunk in every block (strided 2D clear,
+        // never inside a captured graph)
+        const size_t chunk = (size_t)12 * BS * 16;
+        DD_HIP_TRY(hipMemset2DAsync(static_cast<char *>(e.xb.p) + (size_t)r * chunk, chunk * e.W, 0, chunk,
+                                    e.ctx->g.nblocks, e.st()));
+    }
+    SlotState &s = e.S[r];
+    s.state = SLOT_RESTART;
+    s.need_bnorm = true;
+    s.j = 0;
+    s.m0 = m0;
+    s.bnorm = 0;
+    s.info = dd_solve_info{};
+    s.info.status = DD_NOT_CONVERGED;
+    s.owner = owner;
+    s.owner_rhs = owner_rhs;
+    return Status::ok();
+}
+
+Status Engine::extract(int r, double *x_canon)
+{
+    Impl &e = *d;
+    if (r < 0 || r >= e.W) return Status{DD_INVALID_ARG, "engine: bad slot"};
+    return unpack_slot(e.ctx, e.st(), e.xb.p, x_canon, e.W, r);
+}
+
+void Engine::release(int r)
+{
+    if (r >= 0 && r < d->W) d->S[r].state = SLOT_FREE;
+}
+
+// ---- restart phase ----------------------------------------------------------
+Status Engine::launch_restart()
+{
+    Impl &e = *d;
+    e.restart_pending = false;
+    e.bnorm_pending = false;
+    bool any = false, bn = false;
+    for (auto &s : e.S) {
+        any |= s.state == SLOT_RESTART;
+        bn |= s.state == SLOT_RESTART && s.need_bnorm;
+    }
+    if (!any) return Status::ok();
+    SlotArrays &h = e.stage();
+    e.fill_common(h);
+    for (int r = 0; r < ENGINE_MAXW; ++r) {
+        const bool act = r < e.W && e.S[r].state == SLOT_RESTART;
+        h.active[r] = act ? 1 : 0;
+        h.nv[r] = 0;
+        h.dst[r] = 0;
+        h.eta_off[r] = h.psi_off[r] = h.in_off[r] = 0;
+    }
+    DD_TRY(e.upload(h));
+    if (bn) {
+        // |b| of newly admitted slots
+        DD_TRY(e.update_dots(e.bb.as<double2>(), 0, nullptr));
+        DD_TRY(e.reduce(e.resb.as<double2>()));
+        DD_HIP_TRY(hipMemcpyAsync(e.h_resb, e.resb.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+        e.bnorm_pending = true;
+    }
+    // true residual r = b - D x (FP64) for every slot; |r|, max|r|; v_0 for restarting slots
+    DD_TRY(launch_dslash(e.ctx, nullptr, e.W, e.xb.p, DD_F64, e.w.p, DD_F64, DD_F64, e.bb.as<double>(), e.d_m0()));
+    DD_TRY(e.update_dots(e.w.as<double2>(), 0, nullptr));
+    DD_TRY(e.reduce(e.res.as<double2>()));
+    DD_TRY(e.normalize(0, e.res.as<double2>(), e.w.as<double2>()));
+    DD_HIP_TRY(hipMemcpyAsync(e.h_res, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+    DD_HIP_TRY(hipEventRecord(e.ev, e.st()));
+    e.restart_pending = true;
+    return Status::ok();
+}
+
+Status Engine::finish_restart()
+{
+    Impl &e = *d;
+    if (!e.restart_pending) return Status::ok();
+    e.restart_pending = false;
+    DD_HIP_TRY(hipEventSynchronize(e.ev));
+    for (int r = 0; r < e.W; ++r) {
+        SlotState &s = e.S[r];
+        if (s.state != SLOT_RESTART) continue;
+        if (s.need_bnorm && e.bnorm_pending) {
+            double n2 = e.h_resb[(size_t)r * KMAX + K_NORM].x;
+            s.need_bnorm = false;
+            s.bnorm = std::sqrt(n2);
+            if (!std::isfinite(n2)) {
+                s.state = SLOT_DONE;
+                s.info.status = DD_NAN;
+                s.info.rel_residual = n2;
+                continue;
+            }
+        }
+        const double beta = std::sqrt(e.h_res[(size_t)r * KMAX + K_NORM].x);
+        if (!std::isfinite(beta)) {
+            s.state = SLOT_DONE;
+            s.info.status = DD_NAN;
+            s.info.rel_residual = beta;
+            continue;
+        }
+        s.info.rel_residual = s.bnorm > 0 ? beta / s.bnorm : 0.0;
+        if (s.bnorm == 0.0 || beta / s.bnorm <= e.P.tol) {
+            s.state = SLOT_DONE;
+            s.info.status = DD_OK;
+            continue;
+        }
+        if (s.info.restarts >= e.P.max_restarts) {
+            s.state = SLOT_DONE;
+            s.info.status = DD_NOT_CONVERGED;
+            continue;
+        }
+        s.info.restarts++;
+        std::fill(s.g.begin(), s.g.end(), Z64(0.0));
+        s.g[0] = beta;
+        s.j = 0;
+        s.state = SLOT_CYCLE;
+    }
+    return Status::ok();
+}
+
+// ---- Arnoldi step phase -------------------------------------------------------
+Status Engine::launch_step()
+{
+    Impl &e = *d;
+    e.step_pending = false;
+    int nvmax = 0;
+    for (auto &s : e.S)
+        if (s.state == SLOT_CYCLE) nvmax = std::max(nvmax, s.j + 1);
+    if (nvmax == 0) return Status::ok();
+    SlotArrays &h = e.stage();
+    e.fill_common(h);
+    for (int r = 0; r < ENGINE_MAXW; ++r) {
+        const bool act = r < e.W && e.S[r].state == SLOT_CYCLE;
+        const int j = act ? e.S[r].j : 0;
+        h.active[r] = act ? 1 : 0;
+        h.nv[r] = act ? j + 1 : 1;
+        h.dst[r] = act ? j + 1 : 0;
+        h.eta_off[r] = (e.sap_prec == DD_F64) ? (long)j * e.vlen : 0;
+        h.psi_off[r] = (long)j * e.vlen;
+        h.in_off[r] = (long)j * e.vlen;
+    }
+    DD_TRY(e.upload(h));
+    const int bucket = pick_bucket(nvmax);
+    const bool use_graph = e.P.graphs && !e.ctx->prof.on;
+    if (use_graph) {
+        const int key = bucket * 4 + e.sap_prec;
+        auto it = e.graphs.find(key);
+        if (it == e.graphs.end()) {
+            hipGraph_t g = nullptr;
+            DD_HIP_TRY(hipStreamBeginCapture(e.st(), hipStreamCaptureModeThreadLocal));
+            Status cs = e.step_sequence(bucket);
+            hipError_t ce = hipStreamEndCapture(e.st(), &g);
+            if (!cs.good()) {
+                if (g) (void)hipGraphDestroy(g);
+                return cs;
+            }
+            if (ce != hipSuccess) return Status{DD_HIP_ERROR, std::string("graph capture: ") + hipGetErrorString(ce)};
+            hipGraphExec_t ex = nullptr;
+            hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) return Status{DD_HIP_ERROR, std::string("graph instantiate: ") + hipGetErrorString(ie)};
+            it = e.graphs.emplace(key, ex).first;
+        }
+        DD_HIP_TRY(hipGraphLaunch(it->second, e.st()));
+    } else {
+        DD_TRY(e.step_sequence(bucket));
+    }
+    DD_HIP_TRY(hipMemcpyAsync(e.h_res, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+    DD_HIP_TRY(hipMemcpyAsync(e.h_res2, e.res2.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+    DD_HIP_TRY(hipEventRecord(e.ev, e.st()));
+    e.step_pending = true;
+    return Status::ok();
+}
+
+Status Engine::finish_step()
+{
+    Impl &e = *d;
+    if (!e.step_pending) return Status::ok();
+    e.step_pending = false;
+    DD_HIP_TRY(hipEventSynchronize(e.ev));
+    const int m = e.P.m;
+    bool broken = false, any_end = false;
+    int maxlen = 0;
+    for (int r = 0; r < e.W; ++r) {
+        SlotState &s = e.S[r];
+        Z64 *yr = reinterpret_cast<Z64 *>(e.h_y + (size_t)r * ENGINE_MAXM);
+        if (s.state != SLOT_CYCLE) continue;
+        const int j = s.j, nv = j + 1;
+        const double2 *h1 = e.h_res + (size_t)r * KMAX;
+        const double2 *h2 = e.h_res2 + (size_t)r * KMAX;
+        double hh = h2[K_NORM].x;
+        for (int i = 0; i < nv; ++i) {
+            s.H[(size_t)i * m + j] = Z64(h1[i].x, h1[i].y) + Z64(h2[i].x, h2[i].y);
+            hh -= h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+        }
+        const double hn = std::sqrt(std::max(hh, 0.0));
+        s.H[(size_t)(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+            Z64 a = s.H[(size_t)i * m + j], c = s.H[(size_t)(i + 1) * m + j];
+            s.H[(size_t)i * m + j] = s.cs[i] * a + s.sn[i] * c;
+            s.H[(size_t)(i + 1) * m + j] = -std::conj(s.sn[i]) * a + s.cs[i] * c;
+        }
+        Z64 rr;
+        givens(s.H[(size_t)j * m + j], s.H[(size_t)(j + 1) * m + j], s.cs[j], s.sn[j], rr);
+        s.H[(size_t)j * m + j] = rr;
+        s.H[(size_t)(j + 1) * m + j] = 0.0;
+        s.g[j + 1] = -std::conj(s.sn[j]) * s.g[j];
+        s.g[j] = s.cs[j] * s.g[j];
+        s.info.iterations++;
+        s.info.sap_calls++;
+        s.j = j + 1;
+        const bool finite = std::isfinite(hn) && std::isfinite(std::abs(rr));
+        if (!finite) {
+            s.j = j; // drop the broken column; the restart recomputes the true residual
+            broken = true;
+        }
+        if (!finite || hn == 0.0 || std::abs(s.g[j + 1]) / s.bnorm <= e.P.tol || s.j == m) {
+            // end of this slot's cycle: y = R^-1 g, then x += Z y
+            const int len = s.j;
+            for (int i = 0; i < ENGINE_MAXM; ++i) yr[i] = 0.0;
+            for (int i = len - 1; i >= 0; --i) {
+                Z64 acc = s.g[i];
+                for (int k = i + 1; k < len; ++k) acc -= s.H[(size_t)i * m + k] * yr[k];
+                yr[i] = acc / s.H[(size_t)i * m + i];
+            }
+            s.state = SLOT_RESTART;
+            s.cycle_len = len;
+            any_end = true;
+            maxlen = std::max(maxlen, len);
+        }
+    }
+    if (broken && e.sap_prec == DD_F16) {
+        // FP16 range exceeded in the smoother: every slot restarts in FP32
+        e.sap_prec = DD_F32;
+        for (int r = 0; r < e.W; ++r) {
+            SlotState &s = e.S[r];
+            if (s.state != SLOT_CYCLE) continue;
+            Z64 *yr = reinterpret_cast<Z64 *>(e.h_y + (size_t)r * ENGINE_MAXM);
+            const int len = s.j;
+            for (int i = 0; i < ENGINE_MAXM; ++i) yr[i] = 0.0;
+            for (int i = len - 1; i >= 0; --i) {
+                Z64 acc = s.g[i];
+                for (int k = i + 1; k < len; ++k) acc -= s.H[(size_t)i * m + k] * yr[k];
+                yr[i] = acc / s.H[(size_t)i * m + i];
+            }
+            s.state = SLOT_RESTART;
+            s.cycle_len = len;
+            any_end = true;
+            maxlen = std::max(maxlen, len);
+        }
+    }
+    if (any_end && maxlen > 0) {
+        SlotArrays &h = e.stage();
+        e.fill_common(h);
+        for (int r = 0; r < ENGINE_MAXW; ++r) {
+            const bool ended = r < e.W && e.S[r].state == SLOT_RESTART && e.S[r].cycle_len > 0;
+            h.len[r] = ended ? e.S[r].cycle_len : 0;
+            h.active[r] = 0;
+            h.nv[r] = 1;
+            h.dst[r] = 0;
+            h.eta_off[r] = h.psi_off[r] = h.in_off[r] = 0;
+        }
+        for (int r = 0; r < e.W; ++r) e.S[r].cycle_len = 0;
+        DD_TRY(e.upload(h));
+        DD_HIP_TRY(hipMemcpyAsync(e.y.p, e.h_y, (size_t)e.W * ENGINE_MAXM * 16, hipMemcpyHostToDevice, e.st()));
+        DD_TRY(e.combine(maxlen));
+    }
+    return Status::ok();
+}
+
+Status Engine::iterate()
+{
+    DD_TRY(launch_restart());
+    DD_TRY(finish_restart());
+    DD_TRY(launch_step());
+    DD_TRY(finish_step());
+    return Status::ok();
+}
+
+// ---------------------------------------------------------------------------
+// dd_solve: every right-hand side admitted at once into one engine
+// ---------------------------------------------------------------------------
+Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,
+             dd_solve_info *info_out)
+{
+    EngineParams ep;
+    ep.width = nrhs;
+    ep.m = p.m;
+    ep.ncy = p.ncy;
+    ep.nmr = p.nmr;
+    ep.sap_prec = p.sap_prec;
+    ep.tol = p.tol;
+    ep.max_restarts = p.max_restarts;
+    ep.graphs = false;
+    // reuse the context's engine when the shape matches
+    Engine *eng = ctx->engine.get();
+    if (!eng || eng->width() != nrhs || eng->params().m != p.m || eng->params().sap_prec != p.sap_prec) {
+        ctx->engine.reset();
+        std::unique_ptr<Engine, EngineDeleter> ne(new Engine());
+        DD_TRY(ne->init(ctx, ep));
+        ctx->engine = std::move(ne);
+        eng = ctx->engine.get();
+    } else {
+        eng->set_params(ep);
+    }
+    const size_t vstride = (size_t)ctx->g.V * 12 * 2; // doubles per canonical rhs
+    for (int r = 0; r < nrhs; ++r) DD_TRY(eng->admit(r, b + r * vstride, x + r * vstride, m0[r], 0, r));
+    for (int guard = 0; eng->busy_slots() > 0; ++guard) {
+        if (guard > (p.max_restarts + 2) * (p.m + 2) + 8)
+            return Status{DD_HIP_ERROR, "dd_solve: engine made no progress"};
+        DD_TRY(eng->iterate());
+    }
+    Status out = Status::ok();
+    for (int r = 0; r < nrhs; ++r) {
+        DD_TRY(eng->extract(r, x + r * vstride));
+        SlotState &s = eng->slot(r);
+        if (info_out) info_out[r] = s.info;
+        if (s.info.status != DD_OK && out.good())
+            out = Status{(dd_status)s.info.status, "right-hand side " + std::to_string(r) + " did not converge"};
+        eng->release(r);
+    }
+    DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return out;
+}
+
+void Engine::set_params(const EngineParams &p)
+{
+    // tolerance, restarts and smoother cycles may change between solves; the
+    // shape (width, m, precision) may not
+    d->P.tol = p.tol;
+    d->P.max_restarts = p.max_restarts;
+    d->P.ncy = p.ncy;
+    d->P.nmr = p.nmr;
+    d->P.graphs = p.graphs;
+    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
+    d->graphs.clear();
+    d->sap_prec = p.sap_prec;
+}
+
+void EngineDeleter::operator()(Engine *e) const { delete e; }
+
+} // namespace dd

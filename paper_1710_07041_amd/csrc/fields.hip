@@ -221,6 +221,26 @@ __global__ __launch_bounds__(TPB) void k_spinor_unpack(const vec2_t<S> *__restri
     for (int c = 0; c < 12; ++c) stc(dst + c, ldc<double>(src + (long)c * BS));
 }
 
+// one canonical FP64 right-hand side <-> slot `slot` of a width-wide blocked buffer
+__global__ __launch_bounds__(TPB) void k_slot_pack(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                   CanonGeom g, int nblocks, int width, int slot)
+{
+    int b = blockIdx.x, s = threadIdx.x;
+    if (b >= nblocks) return;
+    long x = canon_site(g, b, s);
+    double2 *dst = out + ((long)b * width + slot) * 12 * BS + s;
+    for (int c = 0; c < 12; ++c) dst[(long)c * BS] = in[x * 12 + c];
+}
+__global__ __launch_bounds__(TPB) void k_slot_unpack(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                     CanonGeom g, int nblocks, int width, int slot)
+{
+    int b = blockIdx.x, s = threadIdx.x;
+    if (b >= nblocks) return;
+    long x = canon_site(g, b, s);
+    const double2 *src = in + ((long)b * width + slot) * 12 * BS + s;
+    for (int c = 0; c < 12; ++c) out[x * 12 + c] = src[(long)c * BS];
+}
+
 __global__ __launch_bounds__(TPB) void k_nonfinite(const double *__restrict__ p, long n, int *flag)
 {
     long i = (long)blockIdx.x * TPB + threadIdx.x;
@@ -317,6 +337,26 @@ Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, 
         k_spinor_unpack<float><<<grid, TPB, 0, ctx->stream>>>(static_cast<const float2 *>(blocked), out, cg, g.nblocks, nrhs, g.V);
     else
         k_spinor_unpack<__half><<<grid, TPB, 0, ctx->stream>>>(static_cast<const __half2 *>(blocked), out, cg, g.nblocks, nrhs, g.V);
+    DD_HIP_TRY(hipGetLastError());
+    return Status::ok();
+}
+
+Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot)
+{
+    const GeomHost &g = ctx->g;
+    ProfScope ps(ctx->prof, st, K_PACK, (double)g.V * 24.0 * 16, 0.0);
+    k_slot_pack<<<g.nblocks, TPB, 0, st>>>(reinterpret_cast<const double2 *>(canon), static_cast<double2 *>(blocked),
+                                           canon_geom(g), g.nblocks, width, slot);
+    DD_HIP_TRY(hipGetLastError());
+    return Status::ok();
+}
+
+Status unpack_slot(dd_ctx *ctx, hipStream_t st, const void *blocked, double *canon, int width, int slot)
+{
+    const GeomHost &g = ctx->g;
+    ProfScope ps(ctx->prof, st, K_PACK, (double)g.V * 24.0 * 16, 0.0);
+    k_slot_unpack<<<g.nblocks, TPB, 0, st>>>(static_cast<const double2 *>(blocked), reinterpret_cast<double2 *>(canon),
+                                             canon_geom(g), g.nblocks, width, slot);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }

@@ -35,6 +35,9 @@ struct SArgs {
     int nmr;
     int mode; // 0: psi = 0 everywhere; 1: psi_B = 0 on this colour; 2: general
     double m0[MAXRHS];
+    const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
+    const long *eta_off;  // per-rhs element offsets of eta and psi (nullable)
+    const long *psi_off;
 };
 
 template <typename A> struct Lds {
@@ -270,7 +273,7 @@ template <typename A> __device__ __forceinline__ A wave_sum(A v)
 
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
-    const vec2_t<S> *__restrict__ eta, vec2_t<S> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
+    const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
     const vec2_t<S> *__restrict__ clov, SArgs a)
 {
     constexpr bool REGCLOV = RES::clover, REGLINKS = RES::links;
@@ -299,7 +302,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     }
 
     for (int r = 0; r < a.nrhs; ++r) {
-        const A diag = (A)(4.0 + a.m0[r]);
+        const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
+        const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
+        vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
         const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
         cx<A> rr[12], del[12], q[12];
 #pragma unroll
@@ -387,11 +392,13 @@ typedef Residency<true, false, 1> ResF64;
 
 } // namespace
 
-Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec)
+Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
+               const SapSlots *slots)
 {
-    if (!eta || !psi || !ctx->links[prec].p || !ctx->clover[prec].p)
+    if (!eta || !psi || !ctx->links[prec].p || !ctx->clover[prec].p || (!m0 && !(slots && slots->m0_dev)))
         return Status{DD_INVALID_ARG, "SAP: missing buffer"};
     if (ncy == 0) {
+        if (slots) return Status{DD_INVALID_ARG, "SAP: zero cycles with per-slot offsets"};
         DD_HIP_TRY(hipMemsetAsync(psi, 0, spinor_bytes(ctx->g, prec, nrhs), ctx->stream));
         return Status::ok();
     }
@@ -404,7 +411,12 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
     a.g.nblocks = ctx->g.nblocks;
     a.nrhs = nrhs;
     a.nmr = nmr;
-    for (int r = 0; r < nrhs; ++r) a.m0[r] = m0[r];
+    for (int r = 0; r < nrhs && m0; ++r) a.m0[r] = m0[r];
+    if (slots) {
+        a.m0_dev = slots->m0_dev;
+        a.eta_off = slots->eta_off;
+        a.psi_off = slots->psi_off;
+    }
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;
