@@ -174,6 +174,83 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
                    const dd_params *params, dd_solve_info *info);
 
 /* ---------------------------------------------------------------------------
+ * Serving: continuous batching of solves over resident gauge fields
+ * ---------------------------------------------------------------------------
+ * A server keeps several gauge fields resident (each with its own HIP stream
+ * and a pool of right-hand-side slots sized from the HBM budget).  Requests
+ * are queued first in, first out; a worker thread admits their right-hand
+ * sides into free slots as earlier ones finish, fuses all slots of a field
+ * into multi-RHS launches (the Arnoldi step is replayed as a captured
+ * hipGraph) and overlaps different fields on their streams.  Each slot runs
+ * its own FGMRES(m) to params tol, so a result does not depend on which other
+ * requests share the launches beyond rounding. */
+typedef struct dd_server dd_server;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* solver workspace of all fields together (200 GiB)   */
+    int max_width;           /* slots per field, 1..16 (12)                          */
+    int m;                   /* FGMRES(m), 1..32 (20)                                 */
+    double tol;              /* per right-hand side (1e-10)                          */
+    int max_restarts;        /* (100)                                                 */
+    int ncy, nmr;            /* SAP cycles and MR steps (4, 4)                        */
+    int sap_prec;            /* smoother precision (DD_F32)                           */
+    int use_graphs;          /* replay captured hipGraphs for the Arnoldi step (1)    */
+} dd_server_config;
+
+typedef struct {
+    long requests_done;
+    long rhs_done;
+    long iterations;        /* Arnoldi steps over all finished right-hand sides    */
+    double p50_ms, p99_ms;  /* request latency, submit to completion               */
+    double mean_ms;
+    double wall_s;          /* first submit to last completion                     */
+    double rhs_per_s;       /* rhs_done / wall_s                                   */
+    double busy_s;          /* worker time spent with work on the device           */
+    size_t workspace_bytes; /* reserved slot workspace of all fields                */
+} dd_server_stats;
+
+void dd_server_default_config(dd_server_config *cfg);
+
+/* Create a server on the current HIP device (cfg may be NULL for defaults). */
+dd_status dd_server_create(const dd_server_config *cfg, dd_server **out);
+
+/* Make a gauge field resident (host U as in dd_set_gauge).  width = slots for
+ * this field (0 = max_width), reduced to what the remaining HBM budget allows;
+ * DD_OOM if not even one slot fits.  Fields must be added before the first
+ * submit.  *field_id receives the field's index. */
+dd_status dd_server_add_field(dd_server *s, const int dims[4], const int bcs[4], const double *U_host, double csw,
+                              int width, int *field_id);
+
+/* Slot count and reserved workspace bytes of a field. */
+dd_status dd_server_field_info(const dd_server *s, int field_id, int *width, size_t *workspace_bytes);
+
+/* Queue a request: nrhs right-hand sides b (canonical FP64, device, nrhs*24*V
+ * doubles) on field_id with masses m0 (host, nrhs values); solutions go to x
+ * (canonical FP64 device buffer of the same size).  b and x belong to the
+ * caller and must stay valid until the request completes; the server's
+ * streams are not ordered after the caller's, so all writes to b and x must
+ * have finished before the call.  Returns at once. */
+dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m0, const double *b, double *x,
+                           long *request_id);
+
+/* *done = 1 when the request has finished; then info (host, nrhs entries,
+ * may be NULL) and latency_ms (may be NULL) are filled and the request's
+ * status is returned. */
+dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info *info, double *latency_ms);
+
+/* Block until the request finishes; as dd_server_poll otherwise. */
+dd_status dd_server_wait(dd_server *s, long request_id, dd_solve_info *info, double *latency_ms);
+
+/* Latency percentiles and throughput of the requests finished so far. */
+dd_status dd_server_get_stats(dd_server *s, dd_server_stats *out);
+
+/* Message of the server's last failure. */
+const char *dd_server_last_error(const dd_server *s);
+
+/* Stop the worker (pending requests are abandoned) and free everything. */
+dd_status dd_server_destroy(dd_server *s);
+
+/* ---------------------------------------------------------------------------
  * Measurement (optional; used to price kernels against the hardware roofline)
  * ---------------------------------------------------------------------------
  * Per kernel class: launches, summed duration of the launches measured with

@@ -1,0 +1,440 @@
+// Continuous-batching solve server.
+//
+// Gauge fields stay resident on the device, each with its own HIP stream and
+// its own slot engine (engine.hip).  Requests (one field, one mass per
+// right-hand side, 1..n right-hand sides) enter a FIFO queue.  A worker
+// thread admits right-hand sides into free engine slots as soon as earlier
+// ones finish -- a request does not wait for a batch to drain -- and drives
+// every field's engine phase by phase: it enqueues the restart phase of all
+// fields, then finishes them, then enqueues the Arnoldi step of all fields,
+// then finishes those, so the fields' work overlaps on the device through
+// their streams while each field's slots share fused multi-RHS launches
+// (replayed hipGraphs).  Each field's slot pool is sized once from the HBM
+// budget; a right-hand side is admitted only into a reserved slot, so the
+// workspace never exceeds the budget.  Completion times give per-request
+// latency; the statistics report p50/p99 beside throughput.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "dd_internal.h"
+#include "engine.h"
+
+struct dd_server {
+    dd_server_config cfg{};
+    int device = 0;
+    struct Field {
+        dd_ctx *ctx = nullptr;
+        hipStream_t stream = nullptr;
+        std::unique_ptr<dd::Engine> eng;
+        size_t workspace = 0;
+        std::vector<std::pair<long, int>> slot_owner; // (request, rhs) per slot
+    };
+    std::vector<Field> fields;
+    struct Request {
+        long id = 0;
+        int field = 0;
+        int nrhs = 0;
+        std::vector<double> m0;
+        const double *b = nullptr;
+        double *x = nullptr;
+        int next_rhs = 0; // next right-hand side to admit
+        int done_rhs = 0;
+        std::vector<dd_solve_info> info;
+        double t_submit = 0, t_admit = -1, t_done = 0;
+        bool complete = false;
+        int status = DD_OK;
+    };
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<long> queue;
+    std::unordered_map<long, Request> reqs;
+    long next_id = 1;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    bool started = false;
+    size_t used = 0;
+    std::string err;
+    int fatal = DD_OK;
+    // statistics
+    std::vector<double> latencies_ms;
+    long rhs_done = 0, iterations = 0;
+    double t_first = -1, t_last = 0, busy_s = 0;
+};
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+double percentile(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    double pos = q * (v.size() - 1);
+    size_t lo = (size_t)pos;
+    size_t hi = std::min(lo + 1, v.size() - 1);
+    double f = pos - lo;
+    return v[lo] * (1 - f) + v[hi] * f;
+}
+
+// One pass of the worker: admit, run one engine iteration on every busy
+// field, harvest finished right-hand sides.  Returns false when idle.
+dd::Status work_once(dd_server *s, bool &did_work)
+{
+    did_work = false;
+    struct Adm {
+        int field, slot;
+        long req;
+        int rhs;
+        const double *b;
+        double m0;
+    };
+    std::vector<Adm> adm;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto it = s->queue.begin(); it != s->queue.end();) {
+            dd_server::Request &r = s->reqs[*it];
+            dd_server::Field &f = s->fields[r.field];
+            while (r.next_rhs < r.nrhs) {
+                // a slot is taken when the engine has it free and no admission
+                // of this pass has reserved it yet
+                int slot = -1;
+                for (int k = 0; k < f.eng->width() && slot < 0; ++k)
+                    if (f.eng->slot(k).state == dd::SLOT_FREE && f.slot_owner[k].first == 0) slot = k;
+                if (slot < 0) break;
+                f.slot_owner[slot] = {r.id, r.next_rhs};
+                const size_t vstride = (size_t)f.ctx->g.V * 24;
+                adm.push_back({r.field, slot, r.id, r.next_rhs, r.b + r.next_rhs * vstride, r.m0[r.next_rhs]});
+                if (r.t_admit < 0) r.t_admit = now_s();
+                ++r.next_rhs;
+            }
+            if (r.next_rhs == r.nrhs) it = s->queue.erase(it);
+            else ++it;
+        }
+    }
+    for (auto &a : adm) DD_TRY(s->fields[a.field].eng->admit(a.slot, a.b, nullptr, a.m0, a.req, a.rhs));
+    bool busy = false;
+    for (auto &f : s->fields) busy |= f.eng->busy_slots() > 0;
+    if (!busy) return dd::Status::ok();
+    did_work = true;
+    const double t0 = now_s();
+    for (auto &f : s->fields)
+        if (f.eng->busy_slots()) DD_TRY(f.eng->launch_restart());
+    for (auto &f : s->fields) DD_TRY(f.eng->finish_restart());
+    for (auto &f : s->fields)
+        if (f.eng->busy_slots()) DD_TRY(f.eng->launch_step());
+    for (auto &f : s->fields) DD_TRY(f.eng->finish_step());
+    // harvest finished right-hand sides
+    struct Fin {
+        long req;
+        int rhs;
+        dd_solve_info info;
+    };
+    std::vector<Fin> fin;
+    for (auto &f : s->fields) {
+        bool any = false;
+        for (int r = 0; r < f.eng->width(); ++r) {
+            dd::SlotState &st = f.eng->slot(r);
+            if (st.state != dd::SLOT_DONE) continue;
+            long req = f.slot_owner[r].first;
+            int rhs = f.slot_owner[r].second;
+            double *xdst = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                auto it = s->reqs.find(req);
+                if (it != s->reqs.end()) xdst = it->second.x + (size_t)rhs * f.ctx->g.V * 24;
+            }
+            if (xdst) DD_TRY(f.eng->extract(r, xdst));
+            fin.push_back({req, rhs, st.info});
+            f.eng->release(r);
+            f.slot_owner[r] = {0, 0};
+            any = true;
+        }
+        if (any) DD_HIP_TRY(hipStreamSynchronize(f.stream));
+    }
+    const double t1 = now_s();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy_s += t1 - t0;
+    for (auto &fi : fin) {
+        auto it = s->reqs.find(fi.req);
+        if (it == s->reqs.end()) continue;
+        dd_server::Request &r = it->second;
+        r.info[fi.rhs] = fi.info;
+        if (fi.info.status != DD_OK && r.status == DD_OK) r.status = fi.info.status;
+        s->iterations += fi.info.iterations;
+        ++s->rhs_done;
+        if (++r.done_rhs == r.nrhs) {
+            r.complete = true;
+            r.t_done = t1;
+            s->latencies_ms.push_back((r.t_done - r.t_submit) * 1e3);
+            s->t_last = t1;
+        }
+    }
+    if (!fin.empty()) s->cv_done.notify_all();
+    return dd::Status::ok();
+}
+
+void worker_main(dd_server *s)
+{
+    if (hipSetDevice(s->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->fatal = DD_HIP_ERROR;
+        s->err = "server: hipSetDevice failed in the worker";
+        s->cv_done.notify_all();
+        return;
+    }
+    while (!s->stop.load()) {
+        bool did = false;
+        dd::Status st = work_once(s, did);
+        if (!st.good()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->fatal = st.code;
+            s->err = "server: " + st.msg;
+            for (auto &kv : s->reqs)
+                if (!kv.second.complete) {
+                    kv.second.complete = true;
+                    kv.second.status = st.code;
+                }
+            s->queue.clear();
+            s->cv_done.notify_all();
+            return;
+        }
+        if (!did) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                                [&] { return s->stop.load() || !s->queue.empty(); });
+        }
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+void dd_server_default_config(dd_server_config *c)
+{
+    if (!c) return;
+    c->hbm_budget_bytes = (size_t)200 << 30;
+    c->max_width = 12;
+    c->m = 20;
+    c->tol = 1e-10;
+    c->max_restarts = 100;
+    c->ncy = 4;
+    c->nmr = 4;
+    c->sap_prec = DD_F32;
+    c->use_graphs = 1;
+}
+
+dd_status dd_server_create(const dd_server_config *cfg, dd_server **out)
+{
+    if (!out) return DD_INVALID_ARG;
+    *out = nullptr;
+    dd_server_config c;
+    dd_server_default_config(&c);
+    if (cfg) c = *cfg;
+    if (c.max_width < 1 || c.max_width > dd::ENGINE_MAXW || c.m < 1 || c.m > dd::ENGINE_MAXM || !(c.tol > 0) ||
+        c.ncy < 0 || c.nmr < 0 || c.max_restarts < 0 || (c.sap_prec != DD_F64 && c.sap_prec != DD_F32 && c.sap_prec != DD_F16))
+        return DD_INVALID_ARG;
+    dd_server *s = nullptr;
+    try {
+        s = new dd_server();
+    } catch (...) {
+        return DD_OOM;
+    }
+    s->cfg = c;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return DD_HIP_ERROR;
+    }
+    *out = s;
+    return DD_OK;
+}
+
+const char *dd_server_last_error(const dd_server *s) { return s ? s->err.c_str() : ""; }
+
+dd_status dd_server_add_field(dd_server *s, const int dims[4], const int bcs[4], const double *U_host, double csw,
+                              int width, int *field_id)
+{
+    if (!s || !field_id) return DD_INVALID_ARG;
+    if (s->started) {
+        s->err = "server: fields must be added before the first submit";
+        return DD_INVALID_ARG;
+    }
+    dd_server::Field f;
+    if (hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking) != hipSuccess) {
+        s->err = "server: stream creation failed";
+        return DD_HIP_ERROR;
+    }
+    dd_status st = dd_create(dims, bcs, f.stream, &f.ctx);
+    if (st != DD_OK) {
+        s->err = std::string("server: ") + dd_last_error(nullptr);
+        (void)hipStreamDestroy(f.stream);
+        return st;
+    }
+    st = dd_set_gauge(f.ctx, U_host, csw);
+    if (st != DD_OK) {
+        s->err = std::string("server: ") + dd_last_error(f.ctx);
+        dd_destroy(f.ctx);
+        (void)hipStreamDestroy(f.stream);
+        return st;
+    }
+    const size_t per_slot = dd::Engine::bytes_per_slot(f.ctx->g, s->cfg.m, s->cfg.sap_prec);
+    const size_t left = s->cfg.hbm_budget_bytes > s->used ? s->cfg.hbm_budget_bytes - s->used : 0;
+    int w = width > 0 ? width : s->cfg.max_width;
+    w = std::min<long>(w, (long)(left / per_slot));
+    if (w < 1) {
+        s->err = "server: HBM budget leaves no slot for this field";
+        dd_destroy(f.ctx);
+        (void)hipStreamDestroy(f.stream);
+        return DD_OOM;
+    }
+    dd::EngineParams ep;
+    ep.width = w;
+    ep.m = s->cfg.m;
+    ep.ncy = s->cfg.ncy;
+    ep.nmr = s->cfg.nmr;
+    ep.sap_prec = s->cfg.sap_prec;
+    ep.tol = s->cfg.tol;
+    ep.max_restarts = s->cfg.max_restarts;
+    ep.graphs = s->cfg.use_graphs != 0;
+    f.eng.reset(new dd::Engine());
+    dd::Status es = f.eng->init(f.ctx, ep);
+    if (!es.good()) {
+        s->err = "server: " + es.msg;
+        f.eng.reset();
+        dd_destroy(f.ctx);
+        (void)hipStreamDestroy(f.stream);
+        return es.code;
+    }
+    f.workspace = per_slot * w;
+    f.slot_owner.assign(w, {0, 0});
+    s->used += f.workspace;
+    *field_id = (int)s->fields.size();
+    s->fields.push_back(std::move(f));
+    return DD_OK;
+}
+
+dd_status dd_server_field_info(const dd_server *s, int field_id, int *width, size_t *workspace_bytes)
+{
+    if (!s || field_id < 0 || field_id >= (int)s->fields.size()) return DD_INVALID_ARG;
+    if (width) *width = s->fields[field_id].eng->width();
+    if (workspace_bytes) *workspace_bytes = s->fields[field_id].workspace;
+    return DD_OK;
+}
+
+dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m0, const double *b, double *x,
+                           long *request_id)
+{
+    if (!s || !m0 || !b || !x || !request_id || nrhs < 1) return DD_INVALID_ARG;
+    if (field_id < 0 || field_id >= (int)s->fields.size()) {
+        s->err = "server: unknown field";
+        return DD_INVALID_ARG;
+    }
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) {
+            s->err = "server: non-finite mass";
+            return DD_INVALID_ARG;
+        }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != DD_OK) return (dd_status)s->fatal;
+    if (!s->started) {
+        s->started = true;
+        try {
+            s->worker = std::thread(worker_main, s);
+        } catch (...) {
+            s->err = "server: could not start the worker thread";
+            return DD_HIP_ERROR;
+        }
+    }
+    dd_server::Request r;
+    r.id = s->next_id++;
+    r.field = field_id;
+    r.nrhs = nrhs;
+    r.m0.assign(m0, m0 + nrhs);
+    r.b = b;
+    r.x = x;
+    r.info.assign(nrhs, dd_solve_info{});
+    r.t_submit = now_s();
+    if (s->t_first < 0) s->t_first = r.t_submit;
+    *request_id = r.id;
+    s->queue.push_back(r.id);
+    s->reqs.emplace(r.id, std::move(r));
+    s->cv_work.notify_one();
+    return DD_OK;
+}
+
+dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info *info, double *latency_ms)
+{
+    if (!s || !done) return DD_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(request_id);
+    if (it == s->reqs.end()) return DD_INVALID_ARG;
+    *done = it->second.complete ? 1 : 0;
+    if (it->second.complete) {
+        if (info) std::memcpy(info, it->second.info.data(), sizeof(dd_solve_info) * it->second.nrhs);
+        if (latency_ms) *latency_ms = (it->second.t_done - it->second.t_submit) * 1e3;
+        return (dd_status)it->second.status;
+    }
+    return DD_OK;
+}
+
+dd_status dd_server_wait(dd_server *s, long request_id, dd_solve_info *info, double *latency_ms)
+{
+    if (!s) return DD_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(request_id);
+    if (it == s->reqs.end()) return DD_INVALID_ARG;
+    s->cv_done.wait(lk, [&] { return it->second.complete; });
+    if (info) std::memcpy(info, it->second.info.data(), sizeof(dd_solve_info) * it->second.nrhs);
+    if (latency_ms) *latency_ms = (it->second.t_done - it->second.t_submit) * 1e3;
+    return (dd_status)it->second.status;
+}
+
+dd_status dd_server_get_stats(dd_server *s, dd_server_stats *out)
+{
+    if (!s || !out) return DD_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->requests_done = (long)s->latencies_ms.size();
+    out->rhs_done = s->rhs_done;
+    out->iterations = s->iterations;
+    out->p50_ms = percentile(s->latencies_ms, 0.50);
+    out->p99_ms = percentile(s->latencies_ms, 0.99);
+    double sum = 0;
+    for (double l : s->latencies_ms) sum += l;
+    out->mean_ms = s->latencies_ms.empty() ? 0 : sum / s->latencies_ms.size();
+    out->wall_s = s->t_first < 0 ? 0 : s->t_last - s->t_first;
+    out->rhs_per_s = out->wall_s > 0 ? s->rhs_done / out->wall_s : 0;
+    out->busy_s = s->busy_s;
+    out->workspace_bytes = s->used;
+    return DD_OK;
+}
+
+dd_status dd_server_destroy(dd_server *s)
+{
+    if (!s) return DD_INVALID_ARG;
+    s->stop.store(true);
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    for (auto &f : s->fields) {
+        f.eng.reset();
+        if (f.ctx) dd_destroy(f.ctx);
+        if (f.stream) (void)hipStreamDestroy(f.stream);
+    }
+    delete s;
+    return DD_OK;
+}
+
+} // extern "C"

@@ -39,6 +39,9 @@ EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
     "dd_apply_D_block", "dd_sap", "dd_solve", "dd_profile_enable", "dd_profile_read",
+    "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
+    "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
+    "dd_server_destroy",
 ]
 
 
@@ -55,6 +58,19 @@ class dd_solve_info(ctypes.Structure):
 class dd_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_long), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+class dd_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_width", ctypes.c_int), ("m", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int), ("ncy", ctypes.c_int),
+                ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+
+
+class dd_server_stats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_long), ("rhs_done", ctypes.c_long), ("iterations", ctypes.c_long),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("rhs_per_s", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 _vp, _ip, _d, _i, _l, _sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int, \
@@ -77,6 +93,16 @@ _sigs = {
     "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
     "dd_profile_enable": ([_vp, _i], _i),
+    "dd_server_default_config": ([ctypes.POINTER(dd_server_config)], None),
+    "dd_server_create": ([ctypes.POINTER(dd_server_config), ctypes.POINTER(_vp)], _i),
+    "dd_server_add_field": ([_vp, _ip, _ip, _vp, _d, _i, _ip], _i),
+    "dd_server_field_info": ([_vp, _i, _ip, ctypes.POINTER(_sz)], _i),
+    "dd_server_submit": ([_vp, _i, _i, _dp, _vp, _vp, ctypes.POINTER(_l)], _i),
+    "dd_server_poll": ([_vp, _l, _ip, ctypes.POINTER(dd_solve_info), _dp], _i),
+    "dd_server_wait": ([_vp, _l, ctypes.POINTER(dd_solve_info), _dp], _i),
+    "dd_server_get_stats": ([_vp, ctypes.POINTER(dd_server_stats)], _i),
+    "dd_server_last_error": ([_vp], ctypes.c_char_p),
+    "dd_server_destroy": ([_vp], _i),
     "dd_profile_read": ([_vp, ctypes.POINTER(dd_kernel_stat), _i], _i),
 }
 for _name, (_args, _res) in _sigs.items():
@@ -213,3 +239,90 @@ class Context:
             raise DDError(DD_HIP_ERROR, _lib.dd_last_error(self._h).decode())
         return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
                                        "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(n)}
+
+
+def default_server_config() -> dd_server_config:
+    c = dd_server_config()
+    _lib.dd_server_default_config(ctypes.byref(c))
+    return c
+
+
+class Server:
+    """Continuous-batching solve server over resident gauge fields (wraps dd_server)."""
+
+    def __init__(self, config: dd_server_config | None = None, **kw):
+        c = config if config is not None else default_server_config()
+        for k, v in kw.items():
+            setattr(c, k, PREC.get(v, v) if k == "sap_prec" else v)
+        self._h = _vp()
+        st = _lib.dd_server_create(ctypes.byref(c), ctypes.byref(self._h))
+        if st != DD_OK:
+            raise DDError(st, "dd_server_create failed")
+        self._live = {}
+        self._vol = {}
+
+    def _check(self, st):
+        if st != DD_OK:
+            raise DDError(st, _lib.dd_server_last_error(self._h).decode())
+        return st
+
+    def add_field(self, dims, U, csw, bcs=(1, 1, 1, -1), width=0) -> int:
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        fid = ctypes.c_int()
+        self._check(_lib.dd_server_add_field(self._h, (ctypes.c_int * 4)(*dims), (ctypes.c_int * 4)(*bcs),
+                                             _vp(U.ctypes.data), float(csw), int(width), ctypes.byref(fid)))
+        self._vol[fid.value] = int(np.prod(dims))
+        return fid.value
+
+    def field_info(self, fid):
+        w, b = ctypes.c_int(), ctypes.c_size_t()
+        self._check(_lib.dd_server_field_info(self._h, int(fid), ctypes.byref(w), ctypes.byref(b)))
+        return w.value, b.value
+
+    def submit(self, fid, m0, b, x) -> int:
+        """b, x: canonical complex128 device tensors (nrhs, V, 4, 3); kept alive until waited for."""
+        nrhs = int(b.shape[0])
+        m, mp = _masses(m0, nrhs)
+        # the server's streams are not ordered after the caller's: make b and
+        # x (e.g. a pending zero fill) ready before handing them over
+        torch.cuda.current_stream().synchronize()
+        rid = ctypes.c_long()
+        self._check(_lib.dd_server_submit(self._h, int(fid), nrhs, mp, _vp(_ptr(b)), _vp(_ptr(x)),
+                                          ctypes.byref(rid)))
+        self._live[rid.value] = (b, x, nrhs)
+        return rid.value
+
+    def poll(self, rid):
+        nrhs = self._live[rid][2]
+        done = ctypes.c_int()
+        infos = (dd_solve_info * nrhs)()
+        lat = ctypes.c_double()
+        st = _lib.dd_server_poll(self._h, int(rid), ctypes.byref(done), infos, ctypes.byref(lat))
+        if not done.value:
+            return False, None, None, None
+        return True, st, [{k: getattr(i, k) for k, _ in dd_solve_info._fields_} for i in infos], lat.value
+
+    def wait(self, rid):
+        nrhs = self._live[rid][2]
+        infos = (dd_solve_info * nrhs)()
+        lat = ctypes.c_double()
+        st = _lib.dd_server_wait(self._h, int(rid), infos, ctypes.byref(lat))
+        self._live.pop(rid, None)
+        return st, [{k: getattr(i, k) for k, _ in dd_solve_info._fields_} for i in infos], lat.value
+
+    def stats(self):
+        s = dd_server_stats()
+        self._check(_lib.dd_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in dd_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.dd_server_destroy(self._h)
+            self._h = _vp()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
