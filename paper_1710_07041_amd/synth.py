@@ -56,11 +56,61 @@ def gell_mann() -> np.ndarray:
     return lam
 
 
-def _exp_i_hermitian(H: np.ndarray, eps: float) -> np.ndarray:
+def _exp_i_hermitian_eigh(H: np.ndarray, eps: float) -> np.ndarray:
     """exp(i eps H) for a stack of Hermitian 3x3 matrices (eigendecomposition)."""
     w, W = np.linalg.eigh(H)
     phase = np.exp(1j * eps * w)
-    return np.einsum("...ij,...j,...kj->...ik", W, phase, W.conj())
+    return (W * phase[..., None, :]) @ np.conj(np.swapaxes(W, -1, -2))
+
+
+def _exp_i_hermitian(H: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i Q), Q = eps H traceless Hermitian 3x3, by the Cayley-Hamilton closed
+    form of Morningstar & Peardon, Phys. Rev. D 69 (2004) 054501:
+    exp(iQ) = f0 + f1 Q + f2 Q^2 with f_j from c0 = det Q, c1 = tr Q^2 / 2.
+    Stacks whose spectrum is close to degenerate fall back to the
+    eigendecomposition."""
+    shape = H.shape[:-2]
+    Q = eps * H.reshape(-1, 9)
+    q = [[np.ascontiguousarray(Q[:, 3 * i + j]) for j in range(3)] for i in range(3)]
+    q2 = [[q[i][0] * q[0][k] + q[i][1] * q[1][k] + q[i][2] * q[2][k] for k in range(3)] for i in range(3)]
+    c0 = np.real(q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1])
+                 - q[0][1] * (q[1][0] * q[2][2] - q[1][2] * q[2][0])
+                 + q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0]))
+    c1 = 0.5 * np.real(q2[0][0] + q2[1][1] + q2[2][2])
+    sign = np.where(c0 < 0, -1.0, 1.0)
+    c0 = np.abs(c0)
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    ratio = np.clip(np.divide(c0, c0max, out=np.zeros_like(c0), where=c0max > 0), -1.0, 1.0)
+    theta = np.arccos(ratio)
+    u = np.sqrt(c1 / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1) * np.sin(theta / 3.0)
+    xi0 = np.where(np.abs(w) > 1e-4, np.sin(w) / np.where(w == 0, 1.0, w), 1.0 - w * w / 6.0)
+    e2iu = np.exp(2j * u)
+    emiu = np.exp(-1j * u)
+    cw = np.cos(w)
+    h0 = (u * u - w * w) * e2iu + emiu * (8 * u * u * cw + 2j * u * (3 * u * u + w * w) * xi0)
+    h1 = 2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u * u - w * w) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9 * u * u - w * w
+    bad = np.abs(den) < 1e-6 * np.maximum(c1, 1e-300)
+    den = np.where(bad, 1.0, den)
+    f0, f1, f2 = h0 / den, h1 / den, h2 / den
+    # det Q < 0: exp(iQ) = [exp(-i(-Q))]^+ with f_j(-c0) = (-1)^j conj(f_j(c0))
+    neg = sign < 0
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    U = np.empty((Q.shape[0], 9), dtype=np.complex128)
+    for i in range(3):
+        for j in range(3):
+            e = f1 * q[i][j] + f2 * q2[i][j]
+            if i == j:
+                e += f0
+            U[:, 3 * i + j] = e
+    U = U.reshape(shape + (3, 3))
+    if np.any(bad):
+        U[bad.reshape(shape)] = _exp_i_hermitian_eigh(H[bad.reshape(shape)], eps)
+    return U
 
 
 def random_su3_links(dims, eps: float, seed: int = 0, chunk: int = 1 << 20) -> np.ndarray:
@@ -78,7 +128,7 @@ def random_su3_links(dims, eps: float, seed: int = 0, chunk: int = 1 << 20) -> n
     for start in range(0, nlinks, chunk):
         stop = min(nlinks, start + chunk)
         h = rng.standard_normal((stop - start, 8))
-        H = np.einsum("na,aij->nij", h, lam)
+        H = (h.astype(np.complex128) @ lam.reshape(8, 9)).reshape(-1, 3, 3)
         U[start:stop] = _exp_i_hermitian(H, eps)
     return U.reshape(V, 4, 3, 3)
 
