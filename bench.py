@@ -261,6 +261,13 @@ def main():
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
 
+    # a plain 1 GiB device copy: the reference a counter run scales FETCH/WRITE by
+    ca = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    del ca, cb
+
     for i in range(args.warmup):
         info = one_solve(w["sap"])
         log(f"warmup {i}: {info[0]['iterations']} iterations, residual {info[0]['rel_residual']:.2e}")
@@ -329,6 +336,20 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": rdom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": rdom["frac_hbm"], "traffic": None, "avg_ms": rdom["avg_ms"]}
 
+    # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+    # this workload, copy-calibrated), valid only for the kernel sources it was taken on
+    traffic = {}
+    try:
+        from paper_1710_07041_amd import traffic as tmod
+        rec = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")))
+        if rec.get("source_digest") == tmod.source_digest():
+            traffic = {k: v["traffic_bytes"] for k, v in rec["kernels"].items()}
+    except (OSError, ValueError, KeyError):
+        traffic = {}
+    roof["traffic"] = traffic.get(roof["kernel"])
+    if roof["traffic"]:
+        roof["traffic_over_algorithmic"] = round(roof["traffic"] / prof[dom]["bytes"] * prof[dom]["launches"], 3)
+
     breakdown = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3),
                      "share": round(v["total_ms"] / total_ms, 4),
                      "gbs": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] > 0 else None}
@@ -353,8 +374,8 @@ def main():
                    "smoother": w["sap"], "parallelism": "single GPU"},
         "roofline": roof,
         "roofline_dslash": {"bound": "hbm", "kernel": main_cls, "achieved": rd["gbs"], "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": rd["frac_hbm"], "traffic": None, "avg_ms": rd["avg_ms"],
-                            "bytes_per_launch": rd["bytes_per_launch"]},
+                            "unit": "GB/s", "frac": rd["frac_hbm"], "traffic": traffic.get(main_cls),
+                            "avg_ms": rd["avg_ms"], "bytes_per_launch": rd["bytes_per_launch"]},
         "dslash_frac_hbm": round(dslash_gbs / HBM_PEAK_GBS, 4),
         "dslash_standalone": standalone,
         "time_to_solution_s": {"mixed": round(t_mixed, 4), "fp64": None if t64 is None else round(t64, 4),

@@ -92,6 +92,57 @@ template <typename A> __device__ __forceinline__ void stc(__half2 *p, cx<A> a)
     *p = __floats2half2_rn((float)a.re, (float)a.im);
 }
 
+// Streaming (nontemporal) forms for data touched once per launch (clover
+// terms, outputs): they keep the L2 for the spinor neighbours that are reused.
+template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    T t;
+    if constexpr (sizeof(T) == 4) {
+        unsigned v = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(p));
+        __builtin_memcpy(&t, &v, 4);
+    } else if constexpr (sizeof(T) == 8) {
+        u2 v = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p));
+        __builtin_memcpy(&t, &v, 8);
+    } else {
+        static_assert(sizeof(T) == 16, "2-vector storage of 4, 8 or 16 bytes");
+        u4 v = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(p));
+        __builtin_memcpy(&t, &v, 16);
+    }
+    return t;
+}
+template <typename T> __device__ __forceinline__ void st_stream(T *p, T t)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        unsigned v;
+        __builtin_memcpy(&v, &t, 4);
+        __builtin_nontemporal_store(v, reinterpret_cast<unsigned *>(p));
+    } else if constexpr (sizeof(T) == 8) {
+        u2 v;
+        __builtin_memcpy(&v, &t, 8);
+        __builtin_nontemporal_store(v, reinterpret_cast<u2 *>(p));
+    } else {
+        static_assert(sizeof(T) == 16, "2-vector storage of 4, 8 or 16 bytes");
+        u4 v;
+        __builtin_memcpy(&v, &t, 16);
+        __builtin_nontemporal_store(v, reinterpret_cast<u4 *>(p));
+    }
+}
+template <typename A, typename T> __device__ __forceinline__ cx<A> ldc_stream(const T *p)
+{
+    T v = ld_stream(p);
+    return ldc<A>(&v);
+}
+template <typename A, typename T> __device__ __forceinline__ void stc_stream(T *p, cx<A> a)
+{
+    T v;
+    stc(&v, a);
+    st_stream(p, v);
+}
+
 // ---------------------------------------------------------------------------
 // chiral-basis spin projection.  g_mu = [[0, A_mu], [A_mu^+, 0]] with
 // A_k = -i sigma_k (k = x, y, z) and A_t = 1.  For psi = (u, l) (upper spins
@@ -146,6 +197,36 @@ __device__ __forceinline__ void recon_plus(cx<A> acc[12], const cx<A> h[6], A k)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         cx<A> h0 = k * h[c], h1 = k * h[3 + c];
+        acc[c] = acc[c] + h0;
+        acc[3 + c] = acc[3 + c] + h1;
+        if (MU == 0) { acc[6 + c] = acc[6 + c] + ti(h1);  acc[9 + c] = acc[9 + c] + ti(h0); }
+        if (MU == 1) { acc[6 + c] = acc[6 + c] + h1;      acc[9 + c] = acc[9 + c] - h0; }
+        if (MU == 2) { acc[6 + c] = acc[6 + c] + ti(h0);  acc[9 + c] = acc[9 + c] + tmi(h1); }
+        if (MU == 3) { acc[6 + c] = acc[6 + c] + h0;      acc[9 + c] = acc[9 + c] + h1; }
+    }
+}
+
+// acc += (h, -A^+ h) and acc += (h, A^+ h) without a scale factor
+template <int MU, typename A>
+__device__ __forceinline__ void recon_minus1(cx<A> acc[12], const cx<A> h[6])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<A> h0 = h[c], h1 = h[3 + c];
+        acc[c] = acc[c] + h0;
+        acc[3 + c] = acc[3 + c] + h1;
+        if (MU == 0) { acc[6 + c] = acc[6 + c] + tmi(h1); acc[9 + c] = acc[9 + c] + tmi(h0); }
+        if (MU == 1) { acc[6 + c] = acc[6 + c] - h1;      acc[9 + c] = acc[9 + c] + h0; }
+        if (MU == 2) { acc[6 + c] = acc[6 + c] + tmi(h0); acc[9 + c] = acc[9 + c] + ti(h1); }
+        if (MU == 3) { acc[6 + c] = acc[6 + c] - h0;      acc[9 + c] = acc[9 + c] - h1; }
+    }
+}
+template <int MU, typename A>
+__device__ __forceinline__ void recon_plus1(cx<A> acc[12], const cx<A> h[6])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<A> h0 = h[c], h1 = h[3 + c];
         acc[c] = acc[c] + h0;
         acc[3 + c] = acc[3 + c] + h1;
         if (MU == 0) { acc[6 + c] = acc[6 + c] + ti(h1);  acc[9 + c] = acc[9 + c] + ti(h0); }

@@ -123,11 +123,15 @@ __device__ __forceinline__ void get_link(const cx<A> Ur[4][9], const vec2_t<S> *
     }
 }
 
-// One direction of the LDS exchange with the link given in registers.
+// One direction of the LDS exchange with the link given in registers, already
+// multiplied by the hop factor -1/2.  In-block neighbours carry the boundary
+// sign only when the block spans the whole direction (one block per
+// direction); otherwise the reconstruction is a plain sum.
 template <int MU, typename S, typename A>
 __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
                                              const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
 {
+    const bool wraps = g.nb[MU] == 1; // uniform
     cx<A> h[6], t[6];
     proj_minus<MU>(v, h);
 #pragma unroll
@@ -144,13 +148,15 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
 #pragma unroll
         for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
         su3_mul(U, h, t);
-        recon_minus<MU>(q, t, (A)(sign > 0 ? -0.5f : 0.5f));
+        if (wraps) recon_minus<MU>(q, t, (A)sign);
+        else recon_minus1<MU>(q, t);
     }
     neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
     if (inb) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
-        recon_plus<MU>(q, t, (A)(sign > 0 ? -0.5f : 0.5f));
+        if (wraps) recon_plus<MU>(q, t, (A)sign);
+        else recon_plus1<MU>(q, t);
     }
     __syncthreads();
 }
@@ -187,8 +193,7 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
         exchange_dir<1, S, A>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
         exchange_dir<2, S, A>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
         exchange_dir<3, S, A>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
-        return;
-    }
+    } else {
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
         cx<A> U[9], h[6], t[6];
@@ -218,6 +223,7 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
         }
         __syncthreads();
     }
+    }
 }
 
 // Hops of site s whose neighbour lies outside the block: read psi (and the
@@ -241,6 +247,8 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
         for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
         const A kk = (A)(sign > 0 ? -0.5f : 0.5f);
         if (dir > 0) {
+            // register links already hold -1/2: only the boundary sign remains
+            const A kf = REGLINKS ? (A)sign : kk;
             if (REGLINKS) {
                 // explicit branches: a switch would become a dynamic register index
                 if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
@@ -252,7 +260,7 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
             }
             proj_m(mu, p, h);
             su3_mul(U, h, t);
-            recon_m(mu, q, t, kk);
+            recon_m(mu, q, t, kf);
         } else {
             const vec2_t<S> *u = links + ((long)bn * 4 + mu) * 9 * BS + sn;
 #pragma unroll
@@ -285,13 +293,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     int bc[4];
     block_coords(a.g, b, bc);
 
+    // register-resident links carry the hop factor -1/2
     cx<A> U[REGLINKS ? 4 : 1][9];
     if (REGLINKS) {
 #pragma unroll
         for (int mu = 0; mu < (REGLINKS ? 4 : 1); ++mu) {
             const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) U[mu][e] = ldc<A>(u + e * BS);
+            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc<A>(u + e * BS);
         }
     }
     cx<A> cl[REGCLOV ? 36 : 1];
