@@ -8,7 +8,8 @@
 // projection so each of the eight SU(3) products acts on two spins only.
 // Bandwidth bound: per site the algorithmic traffic is links 72 + clover 72 +
 // spinor in 24 + out 24 reals.  Workgroups are remapped so that each XCD
-// sweeps a contiguous range of blocks (shared L2 for the neighbour faces).
+// sweeps a contiguous range of blocks (shared L2 for the neighbour faces);
+// clover terms and outputs, used once, go through streaming loads/stores.
 #include "dd_device.h"
 #include "dd_internal.h"
 
@@ -98,16 +99,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         for (int c = 0; c < 6; ++c) psi[c] = ldc<A>(in + sp + (6 * k + c) * BS);
         const vec2_t<SF> *cp = clov + ((long)b * 36 + 18 * k) * BS + s;
 #pragma unroll
-        for (int e = 0; e < 18; ++e) cl[e] = ldc<A>(cp + e * BS);
+        for (int e = 0; e < 18; ++e) cl[e] = ldc_stream<A>(cp + e * BS);
         if (k == 0) clover_half_mac(cl, diag, psi, acc);
         else clover_half_mac(cl, diag, psi, acc + 6);
     }
     if (RESID) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc(out + sp + c * BS, ldc<A>(resid + sp + c * BS) - acc[c]);
+        for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - acc[c]);
     } else {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc(out + sp + c * BS, acc[c]);
+        for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, acc[c]);
     }
 }
 

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(TPB) void k_dots(const double2 *__restrict__ V, lon
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0);
-                cmacc(acc[i], ldc<double>(V + ii * vstride + base + c * BS), wc);
+                cmacc(acc[i], ldc_stream<double>(V + ii * vstride + base + c * BS), wc);
             }
         }
     }
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(TPB) void k_update_dots(const double2 *__restrict__
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0); // hc[i] = 0 beyond nv
-                vv[i] = ldc<double>(V + ii * vstride + base + c * BS);
+                vv[i] = ldc_stream<double>(V + ii * vstride + base + c * BS);
                 wc = wc - hc[i] * vv[i];
             }
             if (NV > 0) stc(w + base + c * BS, wc);
@@ -220,10 +220,10 @@ __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restr
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0);
-                wc = wc - hc[i] * ldc<double>(V + ii * vstride + base + c * BS);
+                wc = wc - hc[i] * ldc_stream<double>(V + ii * vstride + base + c * BS);
             }
             C64 v = ni.inv * wc;
-            stc(vnext + base + c * BS, v);
+            stc_stream(vnext + base + c * BS, v);
             if (lp) stc(lp + base + c * BS, ni.scale * v);
         }
     }
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(TPB) void k_combine(double2 *__restrict__ x, const 
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int ii = i < nv ? i : nv - 1; // yc[i] = 0 beyond nv
-                cmac(xc, yc[i], ldc<double>(Z + ii * zstride + base + c * BS));
+                cmac(xc, yc[i], ldc_stream<double>(Z + ii * zstride + base + c * BS));
             }
             stc(x + base + c * BS, xc);
         }
