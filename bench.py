@@ -114,12 +114,13 @@ def roofline_entry(name, st, peak_gbs=HBM_PEAK_GBS):
 
 
 def dslash_standalone(ctx, dims, reps=20):
-    """The operator alone in every precision (and 12 fused right-hand sides in
-    FP32), timed with HIP events on the context stream: GB/s vs the roofline."""
+    """The operator alone in every precision, for one and for 12 fused
+    right-hand sides, timed with HIP events on the context stream: GB/s vs the
+    roofline."""
     import torch
     from paper_1710_07041_amd import synth
     res = {}
-    for prec, n in (("f64", 1), ("f32", 1), ("f16", 1), ("f32", 12)):
+    for prec, n in (("f64", 1), ("f32", 1), ("f16", 1), ("f64", 12), ("f32", 12), ("f16", 12)):
         psi = synth.gaussian_spinor(dims, nrhs=n, seed=3)
         x = torch.from_numpy(psi).to("cuda")
         xb, yb = ctx.empty_blocked(prec, n), ctx.empty_blocked(prec, n)

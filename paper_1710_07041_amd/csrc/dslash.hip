@@ -10,6 +10,7 @@
 // spinor in 24 + out 24 reals.  Workgroups are remapped so that each XCD
 // sweeps a contiguous range of blocks (shared L2 for the neighbour faces);
 // clover terms and outputs, used once, go through streaming loads/stores.
+#include "block_ops.h"
 #include "dd_device.h"
 #include "dd_internal.h"
 
@@ -20,17 +21,53 @@ namespace {
 struct DArgs {
     Geom g;
     int nrhs;
+    int ngroups; // groups of RT right-hand sides (ceil(nrhs / RT))
     int block_id;
     double m0[MAXRHS];
     const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
     const long *in_off;   // per-rhs element offset added to the input (nullable)
 };
 
+// One hop of direction index k = 2 mu + (0: forward, 1: backward) onto acc.
+template <int K, typename A>
+__device__ __forceinline__ void hop_k(const cx<A> psi[12], const cx<A> U[9], A kk, cx<A> acc[12])
+{
+    cx<A> h[6], uh[6];
+    if (K & 1) {
+        proj_plus<K / 2>(psi, h);
+        su3_mul_adj(U, h, uh);
+        recon_plus<K / 2>(acc, uh, kk);
+    } else {
+        proj_minus<K / 2>(psi, h);
+        su3_mul(U, h, uh);
+        recon_minus<K / 2>(acc, uh, kk);
+    }
+}
+
+// The RT right-hand sides of one hop share the link: it is loaded once and
+// applied to each of them.  All RT spinor loads are issued before any
+// arithmetic (no branch between them, so they are in flight together);
+// slots beyond the last right-hand side re-read the first one and their
+// results are never stored.
+template <int K, int RT, typename SI, typename A>
+__device__ __forceinline__ void hop_rhs(const vec2_t<SI> *__restrict__ in, const long ro[RT], const cx<A> U[9],
+                                        A kk, cx<A> acc[RT][12])
+{
+    cx<A> psi[RT][12];
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) psi[rr][c] = ldc<A>(in + ro[rr] + c * BS);
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) hop_k<K, A>(psi[rr], U, kk, acc[rr]);
+}
+
 // The eight hops run as a loop that is deliberately not unrolled: unrolled,
-// the compiler hoists all 168 loads ahead of the arithmetic and spills.
-template <bool BLOCKONLY, typename SI, typename SF, typename A>
+// the compiler hoists all hops' loads ahead of the arithmetic and spills.
+template <bool BLOCKONLY, int RT, typename SI, typename SF, typename A>
 __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const vec2_t<SF> *__restrict__ links,
-                                     const DArgs &a, int b, const int bc[4], int r, int s, cx<A> acc[12])
+                                     const DArgs &a, int b, const int bc[4], int r0, const long ro[RT], int s,
+                                     cx<A> acc[RT][12])
 {
 #pragma unroll 1
     for (int k = 0; k < 8; ++k) {
@@ -39,76 +76,153 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
         bool inb;
         neighbour_rt(a.g, b, bc, s, mu, dir, bn, sn, sign, inb);
         if (BLOCKONLY && !inb) continue;
-        const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r) * 12 * BS + sn;
-        cx<A> psi[12], h[6], uh[6], U[9];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(p + c * BS);
+        const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
+        cx<A> U[9];
         const int lb = dir > 0 ? b : bn, ls = dir > 0 ? s : sn;
         const vec2_t<SF> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
 #pragma unroll
         for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
         const A kk = (A)(-0.5 * sign);
         switch (k) {
-        case 0: proj_minus<0>(psi, h); su3_mul(U, h, uh); recon_minus<0>(acc, uh, kk); break;
-        case 1: proj_plus<0>(psi, h); su3_mul_adj(U, h, uh); recon_plus<0>(acc, uh, kk); break;
-        case 2: proj_minus<1>(psi, h); su3_mul(U, h, uh); recon_minus<1>(acc, uh, kk); break;
-        case 3: proj_plus<1>(psi, h); su3_mul_adj(U, h, uh); recon_plus<1>(acc, uh, kk); break;
-        case 4: proj_minus<2>(psi, h); su3_mul(U, h, uh); recon_minus<2>(acc, uh, kk); break;
-        case 5: proj_plus<2>(psi, h); su3_mul_adj(U, h, uh); recon_plus<2>(acc, uh, kk); break;
-        case 6: proj_minus<3>(psi, h); su3_mul(U, h, uh); recon_minus<3>(acc, uh, kk); break;
-        default: proj_plus<3>(psi, h); su3_mul_adj(U, h, uh); recon_plus<3>(acc, uh, kk); break;
+        case 0: hop_rhs<0, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 1: hop_rhs<1, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 2: hop_rhs<2, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 3: hop_rhs<3, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 4: hop_rhs<4, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 5: hop_rhs<5, RT, SI, A>(p, ro, U, kk, acc); break;
+        case 6: hop_rhs<6, RT, SI, A>(p, ro, U, kk, acc); break;
+        default: hop_rhs<7, RT, SI, A>(p, ro, U, kk, acc); break;
         }
     }
 }
 
 // occupancy target per precision: enough waves per SIMD to keep HBM busy
 // without letting the scheduler hoist all eight hops' loads at once
-template <typename A> struct DslashWaves { static constexpr int value = 4; };
-template <> struct DslashWaves<double> { static constexpr int value = 2; };
+template <typename A, int RT> struct DslashWaves { static constexpr int value = RT > 1 ? 2 : 4; };
+template <int RT> struct DslashWaves<double, RT> { static constexpr int value = 2; };
 
-template <typename SI, typename SO, typename SF, typename A, bool BLOCKONLY, bool RESID>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<A>::value))) void k_dslash(const vec2_t<SI> *__restrict__ in, vec2_t<SO> *__restrict__ out,
+// One 256-thread workgroup per (block, group of RT right-hand sides); the
+// groups of one block follow each other in the launch order, so the block's
+// links and clover terms are re-read from L2.  Streaming clover loads (NTC)
+// only when a block has a single group.
+template <typename SI, typename SO, typename SF, typename A, bool BLOCKONLY, bool RESID, int RT, bool NTC>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<A, RT>::value))) void k_dslash(const vec2_t<SI> *__restrict__ in, vec2_t<SO> *__restrict__ out,
                                                const vec2_t<SF> *__restrict__ links,
                                                const vec2_t<SF> *__restrict__ clov,
                                                const vec2_t<SO> *__restrict__ resid, DArgs a)
 {
-    int b, r;
+    int b, r0;
     if (BLOCKONLY) {
         b = a.block_id;
-        r = 0;
+        r0 = 0;
     } else {
-        int wg = xcd_remap(blockIdx.x, gridDim.x);
-        b = wg / a.nrhs;
-        r = wg - b * a.nrhs;
+        const int wg = xcd_remap(blockIdx.x, gridDim.x);
+        b = wg / a.ngroups;
+        r0 = (wg - b * a.ngroups) * RT;
     }
+    const int nr = a.nrhs - r0 < RT ? a.nrhs - r0 : RT;
     const int s = threadIdx.x;
     int bc[4];
     block_coords(a.g, b, bc);
-    if (a.in_off) in += a.in_off[r];
-    cx<A> acc[12];
+    cx<A> acc[RT][12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = mk<A>(0, 0);
-    hops<BLOCKONLY, SI, SF, A>(in, links, a, b, bc, r, s, acc);
-    const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
-    const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
+    for (int rr = 0; rr < RT; ++rr)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[rr][c] = mk<A>(0, 0);
+    // input of right-hand side r0 + rr relative to that of r0 (plus its own
+    // optional element offset)
+    long ro[RT];
+    A diag[RT];
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+        const int r = r0 + (rr < nr ? rr : 0);
+        ro[rr] = (long)(r - r0) * 12 * BS + (a.in_off ? a.in_off[r] : 0);
+        diag[rr] = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
+    }
+    hops<BLOCKONLY, RT, SI, SF, A>(in, links, a, b, bc, r0, ro, s, acc);
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
-        cx<A> psi[6], cl[18];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) psi[c] = ldc<A>(in + sp + (6 * k + c) * BS);
+        cx<A> cl[18];
         const vec2_t<SF> *cp = clov + ((long)b * 36 + 18 * k) * BS + s;
 #pragma unroll
-        for (int e = 0; e < 18; ++e) cl[e] = ldc_stream<A>(cp + e * BS);
-        if (k == 0) clover_half_mac(cl, diag, psi, acc);
-        else clover_half_mac(cl, diag, psi, acc + 6);
+        for (int e = 0; e < 18; ++e) cl[e] = NTC ? ldc_stream<A>(cp + e * BS) : ldc<A>(cp + e * BS);
+        cx<A> psi[RT][6];
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+            const long sp = ((long)b * a.nrhs + r0) * 12 * BS + s + ro[rr];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) psi[rr][c] = ldc<A>(in + sp + (6 * k + c) * BS);
+        }
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+            if (k == 0) clover_half_mac(cl, diag[rr], psi[rr], acc[rr]);
+            else clover_half_mac(cl, diag[rr], psi[rr], acc[rr] + 6);
+        }
     }
-    if (RESID) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - acc[c]);
-    } else {
+    for (int rr = 0; rr < RT; ++rr) {
+        if (rr < nr) {
+            const long sp = ((long)b * a.nrhs + r0 + rr) * 12 * BS + s;
+            if (RESID) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, acc[c]);
+                for (int c = 0; c < 12; ++c)
+                    stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - acc[rr][c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, acc[rr][c]);
+            }
+        }
+    }
+}
+
+// Block-wise form of the operator: one workgroup per Schwarz block applies
+// the in-block part through the LDS exchange (each link and each in-block
+// spinor read once) and adds the hops that leave the block from memory; the
+// right-hand sides are processed one after the other, with the fields that
+// RES keeps in registers loaded once for all of them.
+template <typename SI, typename SO, typename SF, typename A, typename RES, bool RESID, bool NTC>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_dslash_lds(
+    const vec2_t<SI> *__restrict__ in, vec2_t<SO> *__restrict__ out, const vec2_t<SF> *__restrict__ links,
+    const vec2_t<SF> *__restrict__ clov, const vec2_t<SO> *__restrict__ resid, DArgs a)
+{
+    __shared__ Lds<A> L;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = threadIdx.x;
+    int bc[4];
+    block_coords(a.g, b, bc);
+    // register-resident links carry the hop factor -1/2
+    cx<A> U[RES::links ? 4 : 1][9];
+    if (RES::links) {
+#pragma unroll
+        for (int mu = 0; mu < (RES::links ? 4 : 1); ++mu) {
+            const vec2_t<SF> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc<A>(u + e * BS);
+        }
+    }
+    cx<A> cl[RES::clover ? 36 : 1];
+    if (RES::clover) {
+        const vec2_t<SF> *cp = clov + (long)b * 36 * BS + s;
+#pragma unroll
+        for (int e = 0; e < (RES::clover ? 36 : 1); ++e) cl[e] = ldc<A>(cp + e * BS);
+    }
+    for (int r = 0; r < a.nrhs; ++r) {
+        const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
+        const vec2_t<SI> *__restrict__ inr = in + (a.in_off ? a.in_off[r] : 0);
+        const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
+        cx<A> v[12], q[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = ldc<A>(inr + sp + c * BS);
+        block_apply<SF, A, RES, NTC>(L, a.g, b, bc, s, U, cl, links, clov, diag, v, q);
+        face_hops<SI, SF, A, RES::links>(a.g, b, bc, s, r, a.nrhs, inr, links, U, q);
+        if (RESID) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - q[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, q[c]);
+        }
     }
 }
 
@@ -126,19 +240,57 @@ DArgs make_args(const dd_ctx *ctx, const double *m0, int nrhs)
     return a;
 }
 
+// right-hand sides per workgroup: the accumulators of RT right-hand sides
+// must fit in registers next to the link
+// (FP64: one; FP32 arithmetic: up to three)
+template <typename A> int pick_rt(int nrhs) { return sizeof(A) == 8 ? 1 : (nrhs >= 3 ? 3 : nrhs); }
+
+template <typename SI, typename SO, typename SF, typename A, bool RESID, int RT, bool NTC>
+void launch_rt(dd_ctx *ctx, DArgs a, const void *in, void *out, int field_prec, const void *resid)
+{
+    a.ngroups = (a.nrhs + RT - 1) / RT;
+    k_dslash<SI, SO, SF, A, false, RESID, RT, NTC><<<ctx->g.nblocks * a.ngroups, BS, 0, ctx->stream>>>(
+        static_cast<const vec2_t<SI> *>(in), static_cast<vec2_t<SO> *>(out),
+        static_cast<const vec2_t<SF> *>(ctx->links[field_prec].p), static_cast<const vec2_t<SF> *>(ctx->clover[field_prec].p),
+        static_cast<const vec2_t<SO> *>(resid), a);
+}
+
+template <typename SI, typename SO, typename SF, typename A, typename RES, bool RESID>
+void launch_lds(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_prec, const void *resid)
+{
+    k_dslash_lds<SI, SO, SF, A, RES, RESID, false><<<ctx->g.nblocks, BS, 0, ctx->stream>>>(
+        static_cast<const vec2_t<SI> *>(in), static_cast<vec2_t<SO> *>(out),
+        static_cast<const vec2_t<SF> *>(ctx->links[field_prec].p), static_cast<const vec2_t<SF> *>(ctx->clover[field_prec].p),
+        static_cast<const vec2_t<SO> *>(resid), a);
+}
+
 template <typename SI, typename SO, typename SF, typename A, bool RESID>
 Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_prec, const void *resid)
 {
-    int grid = ctx->g.nblocks * a.nrhs;
     const double V = (double)ctx->g.V, n = a.nrhs;
     const double by = V * (144.0 * sizeof(SF) + 24.0 * n * (sizeof(SI) + sizeof(SO) * (RESID ? 2 : 1)));
     int cls = sizeof(SF) == 8 ? (sizeof(SI) == 8 ? K_DSLASH_F64 : K_DSLASH_F32IN_F64)
                               : (sizeof(SF) == 4 ? K_DSLASH_F32 : K_DSLASH_F16);
     ProfScope ps(ctx->prof, ctx->stream, cls, by, 1848.0 * V * n);
-    k_dslash<SI, SO, SF, A, false, RESID><<<grid, BS, 0, ctx->stream>>>(
-        static_cast<const vec2_t<SI> *>(in), static_cast<vec2_t<SO> *>(out),
-        static_cast<const vec2_t<SF> *>(ctx->links[field_prec].p), static_cast<const vec2_t<SF> *>(ctx->clover[field_prec].p),
-        static_cast<const vec2_t<SO> *>(resid), a);
+    if constexpr (sizeof(SF) == 4) {
+        if (a.nrhs >= 4) {
+            // FP32 fields, many right-hand sides: links and clover in
+            // registers for all of them, block-wise LDS form (measured
+            // faster than the gather form there; FP16 storage and FP64
+            // fields stay with the gather form)
+            launch_lds<SI, SO, SF, A, Residency<true, true, 2>, RESID>(ctx, a, in, out, field_prec, resid);
+            DD_HIP_TRY(hipGetLastError());
+            return Status::ok();
+        }
+    }
+    const int rt = pick_rt<A>(a.nrhs);
+    const bool one = a.nrhs <= rt;
+    if (rt == 1) launch_rt<SI, SO, SF, A, RESID, 1, true>(ctx, a, in, out, field_prec, resid);
+    else if constexpr (sizeof(A) == 4) {
+        if (rt == 2) launch_rt<SI, SO, SF, A, RESID, 2, true>(ctx, a, in, out, field_prec, resid);
+        else if (one) launch_rt<SI, SO, SF, A, RESID, 3, true>(ctx, a, in, out, field_prec, resid);
+        else launch_rt<SI, SO, SF, A, RESID, 3, false>(ctx, a, in, out, field_prec, resid);
+    }
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
@@ -169,18 +321,19 @@ Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, in
 Status launch_dslash_block(dd_ctx *ctx, double m0, int block_id, const void *in, void *out, int prec)
 {
     DArgs a = make_args(ctx, &m0, 1);
+    a.ngroups = 1;
     a.block_id = block_id;
     ProfScope ps(ctx->prof, ctx->stream, K_DSLASH_BLOCK, 256.0 * (144.0 + 48.0) * real_bytes(prec), 1848.0 * 256);
     if (prec == DD_F64)
-        k_dslash<double, double, double, double, true, false><<<1, BS, 0, ctx->stream>>>(
+        k_dslash<double, double, double, double, true, false, 1, true><<<1, BS, 0, ctx->stream>>>(
             static_cast<const double2 *>(in), static_cast<double2 *>(out), ctx->links[DD_F64].as<double2>(),
             ctx->clover[DD_F64].as<double2>(), nullptr, a);
     else if (prec == DD_F32)
-        k_dslash<float, float, float, float, true, false><<<1, BS, 0, ctx->stream>>>(
+        k_dslash<float, float, float, float, true, false, 1, true><<<1, BS, 0, ctx->stream>>>(
             static_cast<const float2 *>(in), static_cast<float2 *>(out), ctx->links[DD_F32].as<float2>(),
             ctx->clover[DD_F32].as<float2>(), nullptr, a);
     else
-        k_dslash<__half, __half, __half, float, true, false><<<1, BS, 0, ctx->stream>>>(
+        k_dslash<__half, __half, __half, float, true, false, 1, true><<<1, BS, 0, ctx->stream>>>(
             static_cast<const __half2 *>(in), static_cast<__half2 *>(out), ctx->links[DD_F16].as<__half2>(),
             ctx->clover[DD_F16].as<__half2>(), nullptr, a);
     DD_HIP_TRY(hipGetLastError());

@@ -20,6 +20,7 @@
 // other colour's psi (and, for -mu hops, the neighbour's link) from memory.
 // Blocks of one colour share no site and read only the other colour's psi,
 // so a sweep needs no synchronisation between workgroups.
+#include "block_ops.h"
 #include "dd_device.h"
 #include "dd_internal.h"
 
@@ -39,245 +40,6 @@ struct SArgs {
     const long *eta_off;  // per-rhs element offsets of eta and psi (nullable)
     const long *psi_off;
 };
-
-template <typename A> struct Lds {
-    cx<A> hf[6][BS]; // projected half spinors for +mu hops
-    cx<A> hb[6][BS]; // U^+ times projected half spinors for -mu hops
-    A red[4][4];
-};
-
-// Direction-dispatched spin algebra for run-time loops over mu (a switch on a
-// uniform value; each case is the compile-time specialisation).
-template <typename A> __device__ __forceinline__ void proj_m(int mu, const cx<A> v[12], cx<A> h[6])
-{
-    switch (mu) {
-    case 0: proj_minus<0>(v, h); break;
-    case 1: proj_minus<1>(v, h); break;
-    case 2: proj_minus<2>(v, h); break;
-    default: proj_minus<3>(v, h); break;
-    }
-}
-template <typename A> __device__ __forceinline__ void proj_p(int mu, const cx<A> v[12], cx<A> h[6])
-{
-    switch (mu) {
-    case 0: proj_plus<0>(v, h); break;
-    case 1: proj_plus<1>(v, h); break;
-    case 2: proj_plus<2>(v, h); break;
-    default: proj_plus<3>(v, h); break;
-    }
-}
-template <typename A> __device__ __forceinline__ void recon_m(int mu, cx<A> q[12], const cx<A> t[6], A k)
-{
-    switch (mu) {
-    case 0: recon_minus<0>(q, t, k); break;
-    case 1: recon_minus<1>(q, t, k); break;
-    case 2: recon_minus<2>(q, t, k); break;
-    default: recon_minus<3>(q, t, k); break;
-    }
-}
-template <typename A> __device__ __forceinline__ void recon_p(int mu, cx<A> q[12], const cx<A> t[6], A k)
-{
-    switch (mu) {
-    case 0: recon_plus<0>(q, t, k); break;
-    case 1: recon_plus<1>(q, t, k); break;
-    case 2: recon_plus<2>(q, t, k); break;
-    default: recon_plus<3>(q, t, k); break;
-    }
-}
-
-// Where the per-site fields live during a sweep: in registers for the whole
-// sweep, or re-read (from L2: one block's fields stay resident while its
-// workgroup runs) at every block application.
-template <bool REGLINKS, bool REGCLOV, int WAVES> struct Residency {
-    static constexpr bool links = REGLINKS, clover = REGCLOV;
-    static constexpr int waves = WAVES;
-};
-
-template <bool REG, typename S, typename A>
-__device__ __forceinline__ void get_link(const cx<A> Ur[4][9], const vec2_t<S> *__restrict__ links, int b, int s,
-                                         int mu, cx<A> U[9])
-{
-    if (REG) {
-        switch (mu) {
-        case 0:
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = Ur[0][e];
-            break;
-        case 1:
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 1 : 0][e];
-            break;
-        case 2:
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 2 : 0][e];
-            break;
-        default:
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = Ur[REG ? 3 : 0][e];
-            break;
-        }
-    } else {
-        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
-    }
-}
-
-// One direction of the LDS exchange with the link given in registers, already
-// multiplied by the hop factor -1/2.  In-block neighbours carry the boundary
-// sign only when the block spans the whole direction (one block per
-// direction); otherwise the reconstruction is a plain sum.
-template <int MU, typename S, typename A>
-__device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
-                                             const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
-{
-    const bool wraps = g.nb[MU] == 1; // uniform
-    cx<A> h[6], t[6];
-    proj_minus<MU>(v, h);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) L.hf[c][s] = h[c];
-    proj_plus<MU>(v, h);
-    su3_mul_adj(U, h, t);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) L.hb[c][s] = t[c];
-    __syncthreads();
-    int bn, sn, sign;
-    bool inb;
-    neighbour<MU, +1>(g, b, bc, s, bn, sn, sign, inb);
-    if (inb) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
-        su3_mul(U, h, t);
-        if (wraps) recon_minus<MU>(q, t, (A)sign);
-        else recon_minus1<MU>(q, t);
-    }
-    neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
-    if (inb) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
-        if (wraps) recon_plus<MU>(q, t, (A)sign);
-        else recon_plus1<MU>(q, t);
-    }
-    __syncthreads();
-}
-
-// q = D_BB v on the block (all threads of the workgroup take part).  The
-// loops over clover halves and directions are kept as loops so that only one
-// step's loads are in flight per thread (unrolled, the compiler hoists them
-// all and spills).
-template <typename S, typename A, typename RES>
-__device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
-                                            const cx<A> Ur[RES::links ? 4 : 1][9], const cx<A> cl[36],
-                                            const vec2_t<S> *__restrict__ links_g,
-                                            const vec2_t<S> *__restrict__ clov_g, A diag, const cx<A> v[12],
-                                            cx<A> q[12])
-{
-#pragma unroll
-    for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
-    if (RES::clover) {
-        clover_mac(cl, diag, v, q);
-    } else {
-#pragma unroll 1
-        for (int k = 0; k < 2; ++k) {
-            cx<A> c2[18];
-            const vec2_t<S> *cp = clov_g + ((long)b * 36 + 18 * k) * BS + s;
-#pragma unroll
-            for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
-            if (k == 0) clover_half_mac<A>(c2, diag, v, q);
-            else clover_half_mac<A>(c2, diag, v + 6, q + 6);
-        }
-    }
-    if constexpr (RES::links) {
-        // links already in registers: no loads to hoist, unroll the directions
-        exchange_dir<0, S, A>(L, g, b, bc, s, Ur[0], v, q);
-        exchange_dir<1, S, A>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
-        exchange_dir<2, S, A>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
-        exchange_dir<3, S, A>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
-    } else {
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        cx<A> U[9], h[6], t[6];
-        get_link<RES::links, S, A>(Ur, links_g, b, s, mu, U);
-        proj_m(mu, v, h);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L.hf[c][s] = h[c];
-        proj_p(mu, v, h);
-        su3_mul_adj(U, h, t);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L.hb[c][s] = t[c];
-        __syncthreads();
-        int bn, sn, sign;
-        bool inb;
-        neighbour_rt(g, b, bc, s, mu, +1, bn, sn, sign, inb);
-        if (inb) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) h[c] = L.hf[c][sn];
-            su3_mul(U, h, t);
-            recon_m(mu, q, t, (A)(sign > 0 ? -0.5f : 0.5f));
-        }
-        neighbour_rt(g, b, bc, s, mu, -1, bn, sn, sign, inb);
-        if (inb) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) t[c] = L.hb[c][sn];
-            recon_p(mu, q, t, (A)(sign > 0 ? -0.5f : 0.5f));
-        }
-        __syncthreads();
-    }
-    }
-}
-
-// Hops of site s whose neighbour lies outside the block: read psi (and the
-// neighbour's link for -mu hops) from memory and accumulate into q.  One hop
-// per loop trip.
-template <typename S, typename A, bool REGLINKS>
-__device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
-                                          const vec2_t<S> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
-                                          const cx<A> Ur[REGLINKS ? 4 : 1][9], cx<A> q[12])
-{
-#pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
-        int bn, sn, sign;
-        bool inb;
-        neighbour_rt(g, b, bc, s, mu, dir, bn, sn, sign, inb);
-        if (inb) continue;
-        cx<A> p[12], h[6], t[6], U[9];
-        const vec2_t<S> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
-        const A kk = (A)(sign > 0 ? -0.5f : 0.5f);
-        if (dir > 0) {
-            // register links already hold -1/2: only the boundary sign remains
-            const A kf = REGLINKS ? (A)sign : kk;
-            if (REGLINKS) {
-                // explicit branches: a switch would become a dynamic register index
-                if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
-                else if (mu == 1) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 1 : 0][e]; }
-                else if (mu == 2) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 2 : 0][e]; }
-                else { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 3 : 0][e]; }
-            } else {
-                get_link<false, S, A>(Ur, links, b, s, mu, U);
-            }
-            proj_m(mu, p, h);
-            su3_mul(U, h, t);
-            recon_m(mu, q, t, kf);
-        } else {
-            const vec2_t<S> *u = links + ((long)bn * 4 + mu) * 9 * BS + sn;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
-            proj_p(mu, p, h);
-            su3_mul_adj(U, h, t);
-            recon_p(mu, q, t, kk);
-        }
-    }
-}
-
-template <typename A> __device__ __forceinline__ A wave_sum(A v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
@@ -333,7 +95,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
             }
-            face_hops<S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+            face_hops<S, S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) rr[c] = rr[c] - q[c];
         }
