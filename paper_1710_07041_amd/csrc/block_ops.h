@@ -205,16 +205,20 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
 }
 
 // Hops of site s whose neighbour lies outside the block: read psi (and the
-// neighbour's link for -mu hops) from memory and accumulate into q.  One hop
-// per loop trip.
+// neighbour's link for -mu hops) from memory and accumulate into q.  In a
+// 4^4 block a site leaves the block in direction mu at most once (forward
+// from the last layer, backward from the first), so one loop trip per
+// direction serves both faces with one set of loads.
 template <typename SP, typename S, typename A, bool REGLINKS>
 __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
                                           const vec2_t<SP> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
                                           const cx<A> Ur[REGLINKS ? 4 : 1][9], cx<A> q[12])
 {
 #pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int l = (s >> (2 * mu)) & 3;
+        if (l != 0 && l != BEXT - 1) continue;
+        const int dir = l == 0 ? -1 : 1;
         int bn, sn, sign;
         bool inb;
         neighbour_rt(g, b, bc, s, mu, dir, bn, sn, sign, inb);
@@ -223,26 +227,27 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
         const vec2_t<SP> *pp = psi + ((long)bn * nrhs + r) * 12 * BS + sn;
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = ldc<A>(pp + c * BS);
+        if (!REGLINKS || dir < 0) {
+            // issued before either branch's arithmetic waits on p
+            const int lb = dir > 0 ? b : bn, ls = dir > 0 ? s : sn;
+            const vec2_t<S> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+        } else {
+            // explicit branches: a switch would become a dynamic register index
+            if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
+            else if (mu == 1) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 1 : 0][e]; }
+            else if (mu == 2) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 2 : 0][e]; }
+            else { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 3 : 0][e]; }
+        }
         const A kk = (A)(sign > 0 ? -0.5f : 0.5f);
         if (dir > 0) {
             // register links already hold -1/2: only the boundary sign remains
             const A kf = REGLINKS ? (A)sign : kk;
-            if (REGLINKS) {
-                // explicit branches: a switch would become a dynamic register index
-                if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
-                else if (mu == 1) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 1 : 0][e]; }
-                else if (mu == 2) { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 2 : 0][e]; }
-                else { for (int e = 0; e < 9; ++e) U[e] = Ur[REGLINKS ? 3 : 0][e]; }
-            } else {
-                get_link<false, S, A>(Ur, links, b, s, mu, U);
-            }
             proj_m(mu, p, h);
             su3_mul(U, h, t);
             recon_m(mu, q, t, kf);
         } else {
-            const vec2_t<S> *u = links + ((long)bn * 4 + mu) * 9 * BS + sn;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
             proj_p(mu, p, h);
             su3_mul_adj(U, h, t);
             recon_p(mu, q, t, kk);

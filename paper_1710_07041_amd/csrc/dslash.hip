@@ -64,34 +64,76 @@ __device__ __forceinline__ void hop_rhs(const vec2_t<SI> *__restrict__ in, const
 
 // The eight hops run as a loop that is deliberately not unrolled: unrolled,
 // the compiler hoists all hops' loads ahead of the arithmetic and spills.
-template <bool BLOCKONLY, int RT, typename SI, typename SF, typename A>
+// With PF the link of the next hop is loaded one trip ahead (registers
+// permitting), so only the spinor loads of a hop wait a full round trip.
+template <int RT, typename SI, typename A>
+__device__ __forceinline__ void hop_switch(int k, const vec2_t<SI> *__restrict__ p, const long ro[RT],
+                                           const cx<A> U[9], A kk, cx<A> acc[RT][12])
+{
+    switch (k) {
+    case 0: hop_rhs<0, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 1: hop_rhs<1, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 2: hop_rhs<2, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 3: hop_rhs<3, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 4: hop_rhs<4, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 5: hop_rhs<5, RT, SI, A>(p, ro, U, kk, acc); break;
+    case 6: hop_rhs<6, RT, SI, A>(p, ro, U, kk, acc); break;
+    default: hop_rhs<7, RT, SI, A>(p, ro, U, kk, acc); break;
+    }
+}
+
+template <typename SF, typename A>
+__device__ __forceinline__ void load_hop_link(const vec2_t<SF> *__restrict__ links, int b, int s, int k, int bn,
+                                              int sn, cx<A> U[9])
+{
+    const int mu = k >> 1;
+    const int lb = (k & 1) ? bn : b, ls = (k & 1) ? sn : s;
+    const vec2_t<SF> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+}
+
+template <bool BLOCKONLY, bool PF, int RT, typename SI, typename SF, typename A>
 __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const vec2_t<SF> *__restrict__ links,
                                      const DArgs &a, int b, const int bc[4], int r0, const long ro[RT], int s,
                                      cx<A> acc[RT][12])
 {
-#pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+    if constexpr (PF && !BLOCKONLY) {
         int bn, sn, sign;
         bool inb;
-        neighbour_rt(a.g, b, bc, s, mu, dir, bn, sn, sign, inb);
-        if (BLOCKONLY && !inb) continue;
-        const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
+        neighbour_rt(a.g, b, bc, s, 0, +1, bn, sn, sign, inb);
         cx<A> U[9];
-        const int lb = dir > 0 ? b : bn, ls = dir > 0 ? s : sn;
-        const vec2_t<SF> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
+        load_hop_link<SF, A>(links, b, s, 0, bn, sn, U);
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
+            const A kk = (A)(-0.5 * sign);
+            int bn2 = bn, sn2 = sn, sign2 = sign;
+            cx<A> Un[9];
+            if (k < 7) { // uniform
+                const int k2 = k + 1;
+                neighbour_rt(a.g, b, bc, s, k2 >> 1, (k2 & 1) ? -1 : 1, bn2, sn2, sign2, inb);
+                load_hop_link<SF, A>(links, b, s, k2, bn2, sn2, Un);
+            }
+            hop_switch<RT, SI, A>(k, p, ro, U, kk, acc);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
-        const A kk = (A)(-0.5 * sign);
-        switch (k) {
-        case 0: hop_rhs<0, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 1: hop_rhs<1, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 2: hop_rhs<2, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 3: hop_rhs<3, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 4: hop_rhs<4, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 5: hop_rhs<5, RT, SI, A>(p, ro, U, kk, acc); break;
-        case 6: hop_rhs<6, RT, SI, A>(p, ro, U, kk, acc); break;
-        default: hop_rhs<7, RT, SI, A>(p, ro, U, kk, acc); break;
+            for (int e = 0; e < 9; ++e) U[e] = Un[e];
+            bn = bn2;
+            sn = sn2;
+            sign = sign2;
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const int mu = k >> 1, dir = (k & 1) ? -1 : 1;
+            int bn, sn, sign;
+            bool inb;
+            neighbour_rt(a.g, b, bc, s, mu, dir, bn, sn, sign, inb);
+            if (BLOCKONLY && !inb) continue;
+            const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
+            cx<A> U[9];
+            load_hop_link<SF, A>(links, b, s, k, bn, sn, U);
+            hop_switch<RT, SI, A>(k, p, ro, U, (A)(-0.5 * sign), acc);
         }
     }
 }
@@ -139,7 +181,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         ro[rr] = (long)(r - r0) * 12 * BS + (a.in_off ? a.in_off[r] : 0);
         diag[rr] = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
     }
-    hops<BLOCKONLY, RT, SI, SF, A>(in, links, a, b, bc, r0, ro, s, acc);
+    hops<BLOCKONLY, sizeof(A) == 8 && RT == 1, RT, SI, SF, A>(in, links, a, b, bc, r0, ro, s, acc);
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
