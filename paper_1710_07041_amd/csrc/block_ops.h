@@ -65,10 +65,13 @@ template <typename A> __device__ __forceinline__ void recon_p(int mu, cx<A> q[12
 
 // Where the per-site fields live during a sweep: in registers for the whole
 // sweep, or re-read (from L2: one block's fields stay resident while its
-// workgroup runs) at every block application.
-template <bool REGLINKS, bool REGCLOV, int WAVES> struct Residency {
-    static constexpr bool links = REGLINKS, clover = REGCLOV;
+// workgroup runs) at every block application.  CLOVH keeps chiral half 0 of
+// the clover term in registers and re-reads only half 1, which halves the
+// clover footprint that has to stay in L2 across the MR steps.
+template <bool REGLINKS, bool REGCLOV, int WAVES, bool CLOVH = false> struct Residency {
+    static constexpr bool links = REGLINKS, clover = REGCLOV, clover_half = CLOVH && !REGCLOV;
     static constexpr int waves = WAVES;
+    static constexpr int ncl = REGCLOV ? 36 : (CLOVH ? 18 : 1); // clover entries held in registers
 };
 
 template <bool REG, typename S, typename A>
@@ -145,15 +148,25 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
 // all and spills).
 template <typename S, typename A, typename RES, bool NTC = false>
 __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
-                                            const cx<A> Ur[RES::links ? 4 : 1][9], const cx<A> cl[36],
+                                            const cx<A> Ur[RES::links ? 4 : 1][9], const cx<A> cl[RES::ncl],
                                             const vec2_t<S> *__restrict__ links_g,
                                             const vec2_t<S> *__restrict__ clov_g, A diag, const cx<A> v[12],
                                             cx<A> q[12])
 {
 #pragma unroll
     for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
-    if (RES::clover) {
+    if constexpr (RES::clover) {
         clover_mac(cl, diag, v, q);
+    } else if constexpr (RES::clover_half) {
+        clover_half_mac<A>(cl, diag, v, q);
+        cx<A> c2[18];
+        const vec2_t<S> *cp = clov_g + ((long)b * 36 + 18) * BS + s;
+        // the address is the same at every MR step: hide that, or the loads
+        // are hoisted out of the MR loop and the half is held in registers
+        asm volatile("" : "+v"(cp));
+#pragma unroll
+        for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
+        clover_half_mac<A>(c2, diag, v + 6, q + 6);
     } else {
 #pragma unroll 1
         for (int k = 0; k < 2; ++k) {

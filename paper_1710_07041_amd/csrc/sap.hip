@@ -41,13 +41,55 @@ struct SArgs {
     const long *psi_off;
 };
 
+// The MR coefficient of one right-hand side: the dot products <q, r> and
+// <q, q> over the block (wavefront shuffles, then a fixed-order combine of the
+// four wavefronts through LDS), alpha = <q, r>/<q, q>; returns false when
+// <q, q> vanishes (uniform over the workgroup).
+template <typename A>
+__device__ __forceinline__ bool mr_alpha(Lds<A> &L, int lane, int wave, const cx<A> q[12], const cx<A> rr[12],
+                                         cx<A> &alpha)
+{
+    A qr_re = 0, qr_im = 0, qq = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        qr_re = fma(q[c].re, rr[c].re, qr_re);
+        qr_re = fma(q[c].im, rr[c].im, qr_re);
+        qr_im = fma(q[c].re, rr[c].im, qr_im);
+        qr_im = fma(-q[c].im, rr[c].re, qr_im);
+        qq = fma(q[c].re, q[c].re, qq);
+        qq = fma(q[c].im, q[c].im, qq);
+    }
+    qr_re = wave_sum(qr_re);
+    qr_im = wave_sum(qr_im);
+    qq = wave_sum(qq);
+    if (lane == 0) {
+        L.red[wave][0] = qr_re;
+        L.red[wave][1] = qr_im;
+        L.red[wave][2] = qq;
+    }
+    __syncthreads();
+    qr_re = ((L.red[0][0] + L.red[1][0]) + L.red[2][0]) + L.red[3][0];
+    qr_im = ((L.red[0][1] + L.red[1][1]) + L.red[2][1]) + L.red[3][1];
+    qq = ((L.red[0][2] + L.red[1][2]) + L.red[2][2]) + L.red[3][2];
+    if (qq == (A)0) return false;
+    alpha = mk<A>(qr_re / qq, qr_im / qq);
+    return true;
+}
+
+// With the half clover in registers, the MR accumulator delta lives in LDS
+// (each thread touches only its own site's entries, so no barrier guards it).
+template <typename A, typename RES> struct DelStore {
+    cx<A> d[RES::clover_half ? 12 : 1][RES::clover_half ? BS : 1];
+};
+
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
     const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
     const vec2_t<S> *__restrict__ clov, SArgs a)
 {
-    constexpr bool REGCLOV = RES::clover, REGLINKS = RES::links;
+    constexpr bool REGLINKS = RES::links;
     __shared__ Lds<A> L;
+    __shared__ DelStore<A, RES> D;
     const int i = xcd_remap(blockIdx.x, gridDim.x);
     const int b = a.blocks[i];
     const int s = threadIdx.x;
@@ -62,14 +104,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         for (int mu = 0; mu < (REGLINKS ? 4 : 1); ++mu) {
             const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc<A>(u + e * BS);
+            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc_stream<A>(u + e * BS);
         }
     }
-    cx<A> cl[REGCLOV ? 36 : 1];
-    if (REGCLOV) {
+    cx<A> cl[RES::ncl];
+    if (RES::clover || RES::clover_half) {
         const vec2_t<S> *cp = clov + (long)b * 36 * BS + s;
 #pragma unroll
-        for (int e = 0; e < (REGCLOV ? 36 : 1); ++e) cl[e] = ldc<A>(cp + e * BS);
+        for (int e = 0; e < RES::ncl; ++e) cl[e] = ldc_stream<A>(cp + e * BS);
     }
 
     for (int r = 0; r < a.nrhs; ++r) {
@@ -77,63 +119,62 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
         vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
         const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
-        cx<A> rr[12], del[12], q[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(eta + sp + c * BS);
-        if (a.mode == 2) {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) del[c] = ldc<A>(psi + sp + c * BS);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) del[c] = mk<A>(0, 0);
-        }
-        if (a.mode != 0) {
-            // rho = eta - (D psi)_B ; psi_B is held in del
+        cx<A> rr[12], q[12];
+        // del = psi_B on entry; MR adds alpha * r to it
+        cx<A> del[RES::clover_half ? 1 : 12];
+        {
+            cx<A> d0[12];
             if (a.mode == 2) {
-                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, del, q);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) d0[c] = ldc_stream<A>(psi + sp + c * BS);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) d0[c] = mk<A>(0, 0);
+            }
+            // q = (D psi)_B: the block part, then the hops from the other colour
+            if (a.mode == 2) {
+                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, d0, q);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
             }
-            face_hops<S, S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+            if constexpr (RES::clover_half) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) rr[c] = rr[c] - q[c];
+                for (int c = 0; c < 12; ++c) D.d[c][s] = d0[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) del[c] = d0[c];
+            }
         }
-        // MR on D_BB: del accumulates alpha * r on top of psi_B
+        if (a.mode != 0) face_hops<S, S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+        // rho = eta - (D psi)_B
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rr[c] = ldc_stream<A>(eta + sp + c * BS) - q[c];
+        // MR on D_BB
         for (int it = 0; it < a.nmr; ++it) {
             block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
-            A qr_re = 0, qr_im = 0, qq = 0;
+            cx<A> alpha;
+            if (!mr_alpha(L, lane, wave, q, rr, alpha)) break;
+            // delta += alpha r, then r -= alpha q
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                qr_re = fma(q[c].re, rr[c].re, qr_re);
-                qr_re = fma(q[c].im, rr[c].im, qr_re);
-                qr_im = fma(q[c].re, rr[c].im, qr_im);
-                qr_im = fma(-q[c].im, rr[c].re, qr_im);
-                qq = fma(q[c].re, q[c].re, qq);
-                qq = fma(q[c].im, q[c].im, qq);
-            }
-            qr_re = wave_sum(qr_re);
-            qr_im = wave_sum(qr_im);
-            qq = wave_sum(qq);
-            if (lane == 0) {
-                L.red[wave][0] = qr_re;
-                L.red[wave][1] = qr_im;
-                L.red[wave][2] = qq;
-            }
-            __syncthreads();
-            qr_re = ((L.red[0][0] + L.red[1][0]) + L.red[2][0]) + L.red[3][0];
-            qr_im = ((L.red[0][1] + L.red[1][1]) + L.red[2][1]) + L.red[3][1];
-            qq = ((L.red[0][2] + L.red[1][2]) + L.red[2][2]) + L.red[3][2];
-            if (qq == (A)0) break; // uniform across the workgroup
-            const cx<A> alpha = mk<A>(qr_re / qq, qr_im / qq);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                cmac(del[c], alpha, rr[c]);
+                if constexpr (RES::clover_half) {
+                    cx<A> d = D.d[c][s];
+                    cmac(d, alpha, rr[c]);
+                    D.d[c][s] = d;
+                } else {
+                    cmac(del[c], alpha, rr[c]);
+                }
                 rr[c] = rr[c] - alpha * q[c];
             }
         }
+        if constexpr (RES::clover_half) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, del[c]);
+            for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, D.d[c][s]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, del[c]);
+        }
     }
 }
 
@@ -157,9 +198,9 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 // links in registers and the clover re-read from L2 per block application
 // beat both "everything in registers" (one workgroup per CU, register
 // pressure) and "everything from L2".
-typedef Residency<true, false, 2> ResF32;
-typedef Residency<true, false, 1> ResF16;
-typedef Residency<true, false, 1> ResF64;
+typedef Residency<true, false, 2, true> ResF32;
+typedef Residency<true, false, 2, true> ResF16;
+typedef Residency<true, false, 1, true> ResF64;
 
 } // namespace
 
