@@ -271,20 +271,21 @@ template <typename A>
 __device__ __forceinline__ void clover_half_mac(const cx<A> c[18], A diag, const cx<A> x[6], cx<A> acc[6])
 {
     A d[6] = {c[0].re, c[0].im, c[1].re, c[1].im, c[2].re, c[2].im};
-    cx<A> y[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) y[i] = (d[i] + diag) * x[i];
+    for (int i = 0; i < 6; ++i) {
+        const A di = d[i] + diag;
+        acc[i].re = fma(di, x[i].re, acc[i].re);
+        acc[i].im = fma(di, x[i].im, acc[i].im);
+    }
     int e = 3;
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int j = i + 1; j < 6; ++j) {
-            cmac(y[i], c[e], x[j]);
-            cmacc(y[j], c[e], x[i]);
+            cmac(acc[i], c[e], x[j]);
+            cmacc(acc[j], c[e], x[i]);
             ++e;
         }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] = acc[i] + y[i];
 }
 
 // acc += (diag + C) p, C = two packed Hermitian 6x6 halves (36 slots)

@@ -53,13 +53,20 @@ template <int K, int RT, typename SI, typename A>
 __device__ __forceinline__ void hop_rhs(const vec2_t<SI> *__restrict__ in, const long ro[RT], const cx<A> U[9],
                                         A kk, cx<A> acc[RT][12])
 {
-    cx<A> psi[RT][12];
+    // held in the storage type until used (half the registers for FP32
+    // input to FP64 arithmetic)
+    vec2_t<SI> raw[RT][12];
 #pragma unroll
     for (int rr = 0; rr < RT; ++rr)
 #pragma unroll
-        for (int c = 0; c < 12; ++c) psi[rr][c] = ldc<A>(in + ro[rr] + c * BS);
+        for (int c = 0; c < 12; ++c) raw[rr][c] = in[ro[rr] + c * BS];
 #pragma unroll
-    for (int rr = 0; rr < RT; ++rr) hop_k<K, A>(psi[rr], U, kk, acc[rr]);
+    for (int rr = 0; rr < RT; ++rr) {
+        cx<A> psi[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&raw[rr][c]);
+        hop_k<K, A>(psi, U, kk, acc[rr]);
+    }
 }
 
 // The eight hops run as a loop that is deliberately not unrolled: unrolled,
@@ -189,17 +196,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         const vec2_t<SF> *cp = clov + ((long)b * 36 + 18 * k) * BS + s;
 #pragma unroll
         for (int e = 0; e < 18; ++e) cl[e] = NTC ? ldc_stream<A>(cp + e * BS) : ldc<A>(cp + e * BS);
-        cx<A> psi[RT][6];
+        vec2_t<SI> raw[RT][6];
 #pragma unroll
         for (int rr = 0; rr < RT; ++rr) {
             const long sp = ((long)b * a.nrhs + r0) * 12 * BS + s + ro[rr];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) psi[rr][c] = ldc<A>(in + sp + (6 * k + c) * BS);
+            for (int c = 0; c < 6; ++c) raw[rr][c] = in[sp + (6 * k + c) * BS];
         }
 #pragma unroll
         for (int rr = 0; rr < RT; ++rr) {
-            if (k == 0) clover_half_mac(cl, diag[rr], psi[rr], acc[rr]);
-            else clover_half_mac(cl, diag[rr], psi[rr], acc[rr] + 6);
+            cx<A> psi[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) psi[c] = ldc<A>(&raw[rr][c]);
+            if (k == 0) clover_half_mac(cl, diag[rr], psi, acc[rr]);
+            else clover_half_mac(cl, diag[rr], psi, acc[rr] + 6);
         }
     }
 #pragma unroll
@@ -284,8 +294,8 @@ DArgs make_args(const dd_ctx *ctx, const double *m0, int nrhs)
 
 // right-hand sides per workgroup: the accumulators of RT right-hand sides
 // must fit in registers next to the link
-// (FP64: one; FP32 arithmetic: up to three)
-template <typename A> int pick_rt(int nrhs) { return sizeof(A) == 8 ? 1 : (nrhs >= 3 ? 3 : nrhs); }
+// (FP64 arithmetic: one -- two already spill; FP32 arithmetic: up to three)
+template <typename SI, typename A> int pick_rt(int nrhs) { return sizeof(A) == 8 ? 1 : (nrhs >= 3 ? 3 : nrhs); }
 
 template <typename SI, typename SO, typename SF, typename A, bool RESID, int RT, bool NTC>
 void launch_rt(dd_ctx *ctx, DArgs a, const void *in, void *out, int field_prec, const void *resid)
@@ -325,7 +335,7 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
             return Status::ok();
         }
     }
-    const int rt = pick_rt<A>(a.nrhs);
+    const int rt = pick_rt<SI, A>(a.nrhs);
     const bool one = a.nrhs <= rt;
     if (rt == 1) launch_rt<SI, SO, SF, A, RESID, 1, true>(ctx, a, in, out, field_prec, resid);
     else if constexpr (sizeof(A) == 4) {
