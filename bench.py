@@ -31,7 +31,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VEC_TFLOPS = 78.6         # MI355X vector FP64
-FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (published, packed)
+FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (published, packed FP32 instructions)
+# The kernels are built with packed FP32 instructions disabled, so their FP32
+# ceiling is one FMA per lane per cycle:
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 WORKLOADS = {
     # name: dims, eps, m0, csw, smoother precision, nrhs, source
@@ -330,8 +334,9 @@ def main():
     rdom = roofline_entry(dom, prof[dom])
     if dom.startswith("sap"):
         # smoother: arithmetic intensity above the FP32 ridge -> priced against the vector ALU peak
-        roof = {"bound": "alu", "kernel": dom, "achieved": rdom["tflops"], "peak": FP32_VEC_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(rdom["tflops"] / FP32_VEC_TFLOPS, 4), "traffic": None,
+        roof = {"bound": "alu", "kernel": dom, "achieved": rdom["tflops"], "peak": round(FP32_UNPACKED_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(rdom["tflops"] / FP32_UNPACKED_TFLOPS, 4), "traffic": None,
+                "peak_published": FP32_VEC_TFLOPS, "frac_published": round(rdom["tflops"] / FP32_VEC_TFLOPS, 4),
                 "hbm_gbs": rdom["gbs"], "hbm_frac": rdom["frac_hbm"], "avg_ms": rdom["avg_ms"]}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": rdom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -337,7 +337,10 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
     }
     const int rt = pick_rt<SI, A>(a.nrhs);
     const bool one = a.nrhs <= rt;
-    if (rt == 1) launch_rt<SI, SO, SF, A, RESID, 1, true>(ctx, a, in, out, field_prec, resid);
+    if (rt == 1) {
+        if (one) launch_rt<SI, SO, SF, A, RESID, 1, true>(ctx, a, in, out, field_prec, resid);
+        else launch_rt<SI, SO, SF, A, RESID, 1, false>(ctx, a, in, out, field_prec, resid);
+    }
     else if constexpr (sizeof(A) == 4) {
         if (rt == 2) launch_rt<SI, SO, SF, A, RESID, 2, true>(ctx, a, in, out, field_prec, resid);
         else if (one) launch_rt<SI, SO, SF, A, RESID, 3, true>(ctx, a, in, out, field_prec, resid);
