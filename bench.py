@@ -151,32 +151,34 @@ SERVE_FIELDS = [((16, 16, 16, 16), 0.5, 1), ((24, 24, 24, 48), 0.5, 2), ((32, 32
 
 def serve_main(args):
     """Serving workload: three resident fields, requests with m0 ~ U[-0.38,-0.2] and 1..12 Gaussian RHS,
-    first a burst (saturation throughput), then Poisson arrivals at 0.7x that load."""
+    first a burst (saturation throughput), then Poisson arrivals at 0.7x that load; the same burst is
+    then served with the FP64 smoother (the plain FP64 GPU path) for comparison."""
     import torch
     from paper_1710_07041_amd import ddsap, synth
     torch.cuda.set_device(0)
-    srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb << 30, max_width=12, use_graphs=1)
-    fids, vols = [], []
     t0 = time.perf_counter()
-    for dims, eps, seed in SERVE_FIELDS:
-        U = synth.random_su3_links(dims, eps, seed=seed)
-        fids.append(srv.add_field(dims, U, 1.0))
-        vols.append(synth.volume(dims))
-        del U
-    widths = [srv.field_info(f)[0] for f in fids]
-    log(f"serving fields resident in {time.perf_counter() - t0:.1f} s, slots per field {widths}")
+    fields = [(dims, synth.random_su3_links(dims, eps, seed=seed)) for dims, eps, seed in SERVE_FIELDS]
+    vols = [synth.volume(dims) for dims, _ in fields]
+    log(f"serving fields generated in {time.perf_counter() - t0:.1f} s")
     gen = torch.Generator(device="cuda")
-    rng = np.random.default_rng(7)
 
-    def make_req(k):
-        fi = int(rng.integers(0, len(fids)))
-        nrhs = int(rng.integers(1, 13))
-        m0 = rng.uniform(-0.38, -0.2, size=nrhs)
-        gen.manual_seed(1000 + k)
-        b = torch.randn((nrhs, vols[fi], 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
-        return fi, m0, b
+    def make_server(prec):
+        srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb << 30, max_width=12, use_graphs=1, sap_prec=prec)
+        fids = [srv.add_field(dims, U, 1.0) for dims, U in fields]
+        return srv, fids, [srv.field_info(f)[0] for f in fids]
 
-    def run(reqs, arrivals):
+    def make_reqs(rng, first, n):
+        out = []
+        for k in range(first, first + n):
+            fi = int(rng.integers(0, len(fields)))
+            nrhs = int(rng.integers(1, 13))
+            m0 = rng.uniform(-0.38, -0.2, size=nrhs)
+            gen.manual_seed(1000 + k)
+            b = torch.randn((nrhs, vols[fi], 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
+            out.append((fi, m0, b))
+        return out
+
+    def run(srv, fids, reqs, arrivals):
         outs = []
         t_start = time.perf_counter()
         for (fi, m0, b), ta in zip(reqs, arrivals):
@@ -199,19 +201,29 @@ def serve_main(args):
                 "mean_ms": round(float(np.mean(lat)), 2), "max_rel_residual": res}
 
     n = args.serve_requests
-    burst = [make_req(k) for k in range(n)]
-    sat = run(burst, [0.0] * n)
-    del burst
+    # mixed precision: FP32 smoother
+    srv, fids, widths = make_server("f32")
+    log(f"mixed server: slots per field {widths}")
+    rng = np.random.default_rng(7)
+    sat = run(srv, fids, make_reqs(rng, 0, n), [0.0] * n)
     torch.cuda.empty_cache()
     log(f"burst: {sat}")
     rate_req = 0.7 * sat["rhs_per_s"] / 6.5  # requests per second at 0.7x the saturation load
-    reqs = [make_req(n + k) for k in range(n)]
-    arr = np.cumsum(rng.exponential(1.0 / rate_req, size=n)) - 0.0
+    reqs = make_reqs(rng, n, n)
+    arr = np.cumsum(rng.exponential(1.0 / rate_req, size=n))
     arr[0] = 0.0
-    pois = run(reqs, list(arr))
+    pois = run(srv, fids, reqs, list(arr))
+    del reqs
     log(f"poisson 0.7x: {pois}")
     st = srv.stats()
     srv.close()
+    torch.cuda.empty_cache()
+    # the same burst with the FP64 smoother
+    srv64, fids64, widths64 = make_server("f64")
+    log(f"FP64 server: slots per field {widths64}")
+    sat64 = run(srv64, fids64, make_reqs(np.random.default_rng(7), 0, n), [0.0] * n)
+    srv64.close()
+    log(f"FP64 burst: {sat64}")
     out = {
         "metric": "serving: RHS/s at saturation, p50/p99 latency under Poisson load (continuous batching)",
         "value": sat["rhs_per_s"], "unit": "RHS/s", "n_gpus": 1, "steps": 2 * n, "warmup": 0,
@@ -220,7 +232,9 @@ def serve_main(args):
         "config": {"workload": "serving: resident 16^4, 24^3x48, 32^3x64 (eps=0.5, csw=1), m0~U[-0.38,-0.2], "
                                "1-12 Gaussian RHS per request, SAP FP32 + FGMRES(20) FP64 to 1e-10, "
                                f"HBM budget {args.serve_budget_gb} GiB", "slots_per_field": widths},
-        "serving": {"saturation": sat, "poisson_0.7x": pois, "server_stats": st},
+        "serving": {"saturation": sat, "poisson_0.7x": pois, "server_stats": st,
+                    "fp64_smoother": {"slots_per_field": widths64, "saturation": sat64,
+                                      "mixed_over_fp64_rhs_per_s": round(sat["rhs_per_s"] / sat64["rhs_per_s"], 3)}},
     }
     print(json.dumps(out))
 

@@ -105,7 +105,46 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
                                      const DArgs &a, int b, const int bc[4], int r0, const long ro[RT], int s,
                                      cx<A> acc[RT][12])
 {
-    if constexpr (PF && !BLOCKONLY) {
+    if constexpr (PF && !BLOCKONLY && RT == 1 && sizeof(SI) == 4) {
+        // FP32 input: both hops of a direction in one trip, so the link that
+        // site x - mu reads for its forward hop is re-read for the backward
+        // hop of site x at once (from L1) rather than a trip later
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            int bf, sf, gf, bb, sb, gb;
+            bool inb;
+            neighbour_rt(a.g, b, bc, s, mu, +1, bf, sf, gf, inb);
+            neighbour_rt(a.g, b, bc, s, mu, -1, bb, sb, gb, inb);
+            vec2_t<SI> pf[12], pb[12];
+            cx<A> Uf[9], Ub[9];
+            const vec2_t<SI> *qf = in + ro[0] + ((long)bf * a.nrhs + r0) * 12 * BS + sf;
+            const vec2_t<SI> *qb = in + ro[0] + ((long)bb * a.nrhs + r0) * 12 * BS + sb;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) pf[c] = qf[c * BS];
+            load_hop_link<SF, A>(links, b, s, 2 * mu, bf, sf, Uf);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) pb[c] = qb[c * BS];
+            load_hop_link<SF, A>(links, b, s, 2 * mu + 1, bb, sb, Ub);
+            cx<A> psi[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&pf[c]);
+            const A kf = (A)(-0.5 * gf), kb = (A)(-0.5 * gb);
+            switch (mu) {
+            case 0: hop_k<0, A>(psi, Uf, kf, acc[0]); break;
+            case 1: hop_k<2, A>(psi, Uf, kf, acc[0]); break;
+            case 2: hop_k<4, A>(psi, Uf, kf, acc[0]); break;
+            default: hop_k<6, A>(psi, Uf, kf, acc[0]); break;
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&pb[c]);
+            switch (mu) {
+            case 0: hop_k<1, A>(psi, Ub, kb, acc[0]); break;
+            case 1: hop_k<3, A>(psi, Ub, kb, acc[0]); break;
+            case 2: hop_k<5, A>(psi, Ub, kb, acc[0]); break;
+            default: hop_k<7, A>(psi, Ub, kb, acc[0]); break;
+            }
+        }
+    } else if constexpr (PF && !BLOCKONLY) {
         int bn, sn, sign;
         bool inb;
         neighbour_rt(a.g, b, bc, s, 0, +1, bn, sn, sign, inb);
