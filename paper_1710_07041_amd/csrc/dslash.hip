@@ -100,12 +100,12 @@ __device__ __forceinline__ void load_hop_link(const vec2_t<SF> *__restrict__ lin
     for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
 }
 
-template <bool BLOCKONLY, bool PF, int RT, typename SI, typename SF, typename A>
+template <bool BLOCKONLY, bool PF, bool PAIR, int RT, typename SI, typename SF, typename A>
 __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const vec2_t<SF> *__restrict__ links,
                                      const DArgs &a, int b, const int bc[4], int r0, const long ro[RT], int s,
                                      cx<A> acc[RT][12])
 {
-    if constexpr (PF && !BLOCKONLY && RT == 1 && sizeof(SI) == 4) {
+    if constexpr (PAIR && !BLOCKONLY && RT == 1 && sizeof(SI) <= 4) {
         // FP32 input: both hops of a direction in one trip, so the link that
         // site x - mu reads for its forward hop is re-read for the backward
         // hop of site x at once (from L1) rather than a trip later
@@ -186,7 +186,7 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
 
 // occupancy target per precision: enough waves per SIMD to keep HBM busy
 // without letting the scheduler hoist all eight hops' loads at once
-template <typename A, int RT> struct DslashWaves { static constexpr int value = RT > 1 ? 2 : 4; };
+template <typename A, int RT> struct DslashWaves { static constexpr int value = RT > 1 ? 2 : 3; };
 template <int RT> struct DslashWaves<double, RT> { static constexpr int value = 2; };
 
 // One 256-thread workgroup per (block, group of RT right-hand sides); the
@@ -227,7 +227,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         ro[rr] = (long)(r - r0) * 12 * BS + (a.in_off ? a.in_off[r] : 0);
         diag[rr] = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
     }
-    hops<BLOCKONLY, sizeof(A) == 8 && RT == 1, RT, SI, SF, A>(in, links, a, b, bc, r0, ro, s, acc);
+    hops<BLOCKONLY, sizeof(A) == 8 && RT == 1, RT == 1 && sizeof(SI) <= 4, RT, SI, SF, A>(in, links, a, b, bc, r0, ro,
+                                                                                      s, acc);
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
