@@ -69,6 +69,10 @@ def lib():
         L.or_mr_block.restype = i_
         L.or_sap.argtypes = [ip, ip, ip, vp, vp, d, vp, vp, i_, i_]
         L.or_sap.restype = i_
+        L.or_mr_block_eo.argtypes = [ip, ip, ip, vp, vp, d, l_, i_, vp, vp, vp]
+        L.or_mr_block_eo.restype = i_
+        L.or_sap_eo.argtypes = [ip, ip, ip, vp, vp, d, vp, vp, i_, i_]
+        L.or_sap_eo.restype = i_
         L.or_fgmres.argtypes = [ip, ip, ip, vp, vp, d, vp, vp, i_, d, i_, i_, i_, PRECOND_FN, vp,
                                 ctypes.POINTER(OrInfo)]
         L.or_fgmres.restype = i_
@@ -161,12 +165,26 @@ def mr_block(dims, block, U, C, m0, block_id, rho, nmr, bc=DEFAULT_BC):
     return delta, r, steps
 
 
-def sap(dims, block, U, C, m0, eta, ncy, nmr, bc=DEFAULT_BC):
+def mr_block_eo(dims, block, U, C, m0, block_id, rho, nmr, bc=DEFAULT_BC):
+    """Even-odd preconditioned block solve; returns (delta, r_schur, steps)."""
+    V = int(np.prod(dims))
+    U, C, rho = _c(U, (V, 4, 3, 3)), _c(C, (V, 12, 12)), _c(rho, (V, 4, 3))
+    delta = np.zeros_like(rho)
+    r = np.zeros_like(rho)
+    steps = lib().or_mr_block_eo(_ivec(dims), _ivec(block), _ivec(bc), _p(U), _p(C), float(m0), int(block_id),
+                                 int(nmr), _p(rho), _p(delta), _p(r))
+    if steps < 0:
+        raise ValueError("invalid blocking or block id")
+    return delta, r, steps
+
+
+def sap(dims, block, U, C, m0, eta, ncy, nmr, bc=DEFAULT_BC, eo=False):
+    """Algorithm S; ``eo`` selects the even-odd preconditioned block solve."""
     V = int(np.prod(dims))
     U, C, eta = _c(U, (V, 4, 3, 3)), _c(C, (V, 12, 12)), _c(eta, (V, 4, 3))
     psi = np.zeros_like(eta)
-    rc = lib().or_sap(_ivec(dims), _ivec(block), _ivec(bc), _p(U), _p(C), float(m0), _p(eta), _p(psi),
-                      int(ncy), int(nmr))
+    fn = lib().or_sap_eo if eo else lib().or_sap
+    rc = fn(_ivec(dims), _ivec(block), _ivec(bc), _p(U), _p(C), float(m0), _p(eta), _p(psi), int(ncy), int(nmr))
     if rc != 0:
         raise ValueError("invalid blocking or parameters")
     return psi

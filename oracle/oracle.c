@@ -471,6 +471,275 @@ int or_sap(const int L[4], const int B[4], const int bcs[4], const double comple
 }
 
 /* ------------------------------------------------------------------------ */
+/* Even-odd preconditioned block solve (SAP variant with the site-parity     */
+/* Schur complement inside each block; not in the paper, a standard SAP      */
+/* refinement, cf. Luescher 2004 Sec. 4 and DeGrand-Rossi even-odd           */
+/* preconditioning).  Site parity p(x) = (x + y + z + t) mod 2.  On block B, */
+/* with A = (4 + m0) + C (site-local) and H the in-block hops,               */
+/*   D_BB = [[A_ee, H_eo], [H_oe, A_oo]],                                    */
+/*   S    = A_ee - H_eo A_oo^-1 H_oe          (on the even sites of B),      */
+/* the block system D_BB delta = rho is solved approximately as              */
+/*   rhat_e  = rho_e - H_eo A_oo^-1 rho_o,                                   */
+/*   delta_e = nmr MR steps for S delta_e = rhat_e from delta_e = 0,         */
+/*   delta_o = A_oo^-1 (rho_o - H_oe delta_e).                               */
+/* ------------------------------------------------------------------------ */
+static int site_parity(const int L[4], long x)
+{
+    int c[4];
+    coords_of(L, x, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+/* y = ((4 + m0) + C_x)^-1 b by Gaussian elimination with partial pivoting. */
+static void site_solve(const double complex *Cx, double m0, const double complex *b, double complex *y)
+{
+    double complex M[12][13];
+    for (int i = 0; i < 12; ++i) {
+        for (int j = 0; j < 12; ++j) M[i][j] = Cx[i * 12 + j] + (i == j ? 4.0 + m0 : 0.0);
+        M[i][12] = b[i];
+    }
+    for (int k = 0; k < 12; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < 12; ++i)
+            if (cabs(M[i][k]) > cabs(M[piv][k])) piv = i;
+        if (piv != k)
+            for (int j = 0; j <= 12; ++j) {
+                double complex t = M[k][j];
+                M[k][j] = M[piv][j];
+                M[piv][j] = t;
+            }
+        for (int i = k + 1; i < 12; ++i) {
+            double complex f = M[i][k] / M[k][k];
+            for (int j = k; j <= 12; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    for (int i = 11; i >= 0; --i) {
+        double complex acc = M[i][12];
+        for (int j = i + 1; j < 12; ++j) acc -= M[i][j] * y[j];
+        y[i] = acc / M[i][i];
+    }
+}
+
+/* out(x) = sum of the in-block hops of D applied to `in`, at site x only
+ * (the same hop terms as dirac_site, without the site-local part). */
+static void hop_site(const int L[4], const int bcs[4], const double complex *U, const double complex *in, long x,
+                     const block_filter *filt, double complex *out /* [12] */)
+{
+    for (int i = 0; i < 12; ++i) out[i] = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        double complex chi[12], gchi[12];
+        int wrapped;
+        long xf = shift(L, x, mu, +1, &wrapped);
+        if (in_block(filt, xf)) {
+            double sign = wrapped ? (double)bcs[mu] : 1.0;
+            colour_apply(link(U, x, mu), 0, in + xf * 12, chi);
+            spin_apply(GAMMA[mu], chi, gchi);
+            for (int i = 0; i < 12; ++i) out[i] -= 0.5 * sign * (chi[i] - gchi[i]);
+        }
+        long xb = shift(L, x, mu, -1, &wrapped);
+        if (in_block(filt, xb)) {
+            double sign = wrapped ? (double)bcs[mu] : 1.0;
+            colour_apply(link(U, xb, mu), 1, in + xb * 12, chi);
+            spin_apply(GAMMA[mu], chi, gchi);
+            for (int i = 0; i < 12; ++i) out[i] -= 0.5 * sign * (chi[i] + gchi[i]);
+        }
+    }
+}
+
+/* out = H in on the block sites of parity `par` (in must vanish there). */
+static void hop_parity(const int L[4], const int B[4], const int bcs[4], const double complex *U, const int bc[4],
+                       int par, const double complex *in, double complex *out)
+{
+    block_filter f = {L, B, {bc[0], bc[1], bc[2], bc[3]}};
+    long nb = block_volume(B);
+    for (long k = 0; k < nb; ++k) {
+        long x = block_site(L, B, bc, k);
+        if (site_parity(L, x) == par) hop_site(L, bcs, U, in, x, &f, out + x * 12);
+    }
+}
+
+/* Zero the block sites of parity `par` of a whole-lattice array. */
+static void zero_parity(const int L[4], const int B[4], const int bc[4], int par, double complex *a)
+{
+    long nb = block_volume(B);
+    for (long k = 0; k < nb; ++k) {
+        long x = block_site(L, B, bc, k);
+        if (site_parity(L, x) == par)
+            for (int i = 0; i < 12; ++i) a[x * 12 + i] = 0;
+    }
+}
+
+/* q_e = S r_e = A_ee r_e - H_eo A_oo^-1 H_oe r_e.  r, q, t whole-lattice
+ * scratch; r must vanish on the odd block sites; q and t are overwritten on
+ * the block. */
+static void schur_apply(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+                        const double complex *C, double m0, const int bc[4], const double complex *r,
+                        double complex *q, double complex *t)
+{
+    long nb = block_volume(B);
+    zero_parity(L, B, bc, 0, t);
+    hop_parity(L, B, bcs, U, bc, 1, r, t); /* t_o = H_oe r_e */
+    for (long k = 0; k < nb; ++k) {        /* t_o = A_oo^-1 t_o */
+        long x = block_site(L, B, bc, k);
+        if (site_parity(L, x) == 1) {
+            double complex y[12];
+            site_solve(C + x * 144, m0, t + x * 12, y);
+            for (int i = 0; i < 12; ++i) t[x * 12 + i] = y[i];
+        }
+    }
+    zero_parity(L, B, bc, 1, q);
+    hop_parity(L, B, bcs, U, bc, 0, t, q); /* q_e = H_eo t_o */
+    for (long k = 0; k < nb; ++k) {        /* q_e = A_ee r_e - q_e */
+        long x = block_site(L, B, bc, k);
+        if (site_parity(L, x) == 0) {
+            const double complex *Cx = C + x * 144;
+            for (int i = 0; i < 12; ++i) {
+                double complex acc = (4.0 + m0) * r[x * 12 + i];
+                for (int j = 0; j < 12; ++j) acc += Cx[i * 12 + j] * r[x * 12 + j];
+                q[x * 12 + i] = acc - q[x * 12 + i];
+            }
+        }
+    }
+}
+
+static int mr_block_eo_coords(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+                              const double complex *C, double m0, const int bc[4], int nmr,
+                              const double complex *rho, double complex *delta, double complex *r,
+                              double complex *q, double complex *t)
+{
+    long nb = block_volume(B);
+    /* t_o = A_oo^-1 rho_o ; r_e = rho_e - H_eo t_o ; delta = 0 */
+    for (long k = 0; k < nb; ++k) {
+        long x = block_site(L, B, bc, k);
+        for (int i = 0; i < 12; ++i) {
+            delta[x * 12 + i] = 0;
+            t[x * 12 + i] = 0;
+        }
+        if (site_parity(L, x) == 1) site_solve(C + x * 144, m0, rho + x * 12, t + x * 12);
+    }
+    zero_parity(L, B, bc, 1, q);
+    hop_parity(L, B, bcs, U, bc, 0, t, q);
+    for (long k = 0; k < nb; ++k) {
+        long x = block_site(L, B, bc, k);
+        int even = site_parity(L, x) == 0;
+        for (int i = 0; i < 12; ++i) r[x * 12 + i] = even ? rho[x * 12 + i] - q[x * 12 + i] : 0;
+    }
+    int steps = 0;
+    for (int it = 0; it < nmr; ++it) {
+        schur_apply(L, B, bcs, U, C, m0, bc, r, q, t);
+        double complex qr = 0;
+        double qq = 0;
+        for (long k = 0; k < nb; ++k) {
+            long x = block_site(L, B, bc, k);
+            if (site_parity(L, x) != 0) continue;
+            for (int i = 0; i < 12; ++i) {
+                qr += conj(q[x * 12 + i]) * r[x * 12 + i];
+                qq += creal(conj(q[x * 12 + i]) * q[x * 12 + i]);
+            }
+        }
+        if (qq == 0.0) break;
+        double complex alpha = qr / qq;
+        for (long k = 0; k < nb; ++k) {
+            long x = block_site(L, B, bc, k);
+            if (site_parity(L, x) != 0) continue;
+            for (int i = 0; i < 12; ++i) {
+                delta[x * 12 + i] += alpha * r[x * 12 + i];
+                r[x * 12 + i] -= alpha * q[x * 12 + i];
+            }
+        }
+        ++steps;
+    }
+    /* delta_o = A_oo^-1 (rho_o - H_oe delta_e) */
+    zero_parity(L, B, bc, 0, t);
+    hop_parity(L, B, bcs, U, bc, 1, delta, t);
+    for (long k = 0; k < nb; ++k) {
+        long x = block_site(L, B, bc, k);
+        if (site_parity(L, x) == 1) {
+            double complex rhs[12];
+            for (int i = 0; i < 12; ++i) rhs[i] = rho[x * 12 + i] - t[x * 12 + i];
+            site_solve(C + x * 144, m0, rhs, delta + x * 12);
+        }
+    }
+    return steps;
+}
+
+int or_mr_block_eo(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+                   const double complex *C, double m0, long block_id, int nmr, const double complex *rho,
+                   double complex *delta, double complex *r_out)
+{
+    if (!blocking_valid(L, B) || block_id < 0 || block_id >= num_blocks(L, B) || nmr < 0) return -1;
+    long V = volume_of(L);
+    double complex *r = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *q = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *t = calloc((size_t)V * 12, sizeof(double complex));
+    if (!r || !q || !t) {
+        free(r); free(q); free(t);
+        return -1;
+    }
+    int bc[4];
+    block_coords(L, B, block_id, bc);
+    int steps = mr_block_eo_coords(L, B, bcs, U, C, m0, bc, nmr, rho, delta, r, q, t);
+    if (r_out) {
+        long nb = block_volume(B);
+        for (long k = 0; k < nb; ++k) {
+            long x = block_site(L, B, bc, k);
+            for (int i = 0; i < 12; ++i) r_out[x * 12 + i] = r[x * 12 + i];
+        }
+    }
+    free(r); free(q); free(t);
+    return steps;
+}
+
+/* Algorithm S with the even-odd block solve in place of Algorithm M. */
+int or_sap_eo(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+              const double complex *C, double m0, const double complex *eta, double complex *psi,
+              int ncy, int nmr)
+{
+    if (!blocking_valid(L, B) || ncy < 0 || nmr < 0) return -1;
+    long V = volume_of(L);
+    long nblk = num_blocks(L, B);
+    long nb = block_volume(B);
+    double complex *rho = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *delta = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *r = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *q = calloc((size_t)V * 12, sizeof(double complex));
+    double complex *t = calloc((size_t)V * 12, sizeof(double complex));
+    if (!rho || !delta || !r || !q || !t) {
+        free(rho); free(delta); free(r); free(q); free(t);
+        return -1;
+    }
+    memset(psi, 0, sizeof(double complex) * (size_t)V * 12);
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (long id = 0; id < nblk; ++id) {
+                int bc[4];
+                block_coords(L, B, id, bc);
+                if (block_colour(bc) != colour) continue;
+                for (long k = 0; k < nb; ++k) {
+                    long x = block_site(L, B, bc, k);
+                    double complex dpsi[12];
+                    dirac_site(L, bcs, U, C + x * 144, m0, psi, x, NULL, dpsi);
+                    for (int i = 0; i < 12; ++i) rho[x * 12 + i] = eta[x * 12 + i] - dpsi[i];
+                }
+            }
+#pragma omp parallel for schedule(dynamic, 1)
+            for (long id = 0; id < nblk; ++id) {
+                int bc[4];
+                block_coords(L, B, id, bc);
+                if (block_colour(bc) != colour) continue;
+                mr_block_eo_coords(L, B, bcs, U, C, m0, bc, nmr, rho, delta, r, q, t);
+                for (long k = 0; k < nb; ++k) {
+                    long x = block_site(L, B, bc, k);
+                    for (int i = 0; i < 12; ++i) psi[x * 12 + i] += delta[x * 12 + i];
+                }
+            }
+        }
+    free(rho); free(delta); free(r); free(q); free(t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Vector helpers for FGMRES (fixed summation order)                         */
 /* ------------------------------------------------------------------------ */
 static double complex vdot(long n, const double complex *a, const double complex *b)

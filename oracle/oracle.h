@@ -89,6 +89,22 @@ int or_sap(const int L[4], const int B[4], const int bcs[4], const double comple
            const double complex *C, double m0, const double complex *eta, double complex *psi,
            int ncy, int nmr);
 
+/* Even-odd preconditioned block solve on block `block_id` (site parity
+ * (x+y+z+t) mod 2): nmr MR steps on the Schur complement
+ * S = A_ee - H_eo A_oo^-1 H_oe for rhat_e = rho_e - H_eo A_oo^-1 rho_o, then
+ * delta_o = A_oo^-1 (rho_o - H_oe delta_e); A = (4+m0) + C, H the in-block
+ * hops.  r_out (may be NULL) receives the final Schur residual on the even
+ * sites (zero on the odd ones).  Returns the MR steps taken, -1 on invalid
+ * blocking. */
+int or_mr_block_eo(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+                   const double complex *C, double m0, long block_id, int nmr,
+                   const double complex *rho, double complex *delta, double complex *r_out);
+
+/* Algorithm S with the even-odd block solve in place of Algorithm M. */
+int or_sap_eo(const int L[4], const int B[4], const int bcs[4], const double complex *U,
+              const double complex *C, double m0, const double complex *eta, double complex *psi,
+              int ncy, int nmr);
+
 /* Algorithm G: FGMRES(m) with right preconditioning.  x holds x0 on entry
  * and the solution on exit.  Preconditioner: `pre` if non-NULL, else SAP with
  * (ncy, nmr) if ncy > 0, else the identity. */
