@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define DD_ABI_VERSION 1
+#define DD_ABI_VERSION 2
 #define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
 
 typedef enum {
@@ -90,6 +90,7 @@ typedef struct {
     int ncy;          /* SAP cycles per preconditioner call; 0 = no precond (4) */
     int nmr;          /* MR steps per block and sweep (4)                        */
     int sap_prec;     /* dd_prec of the smoother (DD_F32)                        */
+    int sap_eo;       /* 1: even-odd preconditioned block solves (dd_sap_eo), 0 */
 } dd_params;
 
 /* Per right-hand-side result of dd_solve. */
@@ -163,6 +164,18 @@ dd_status dd_apply_D_block(dd_ctx *ctx, double m0, long block_id, const void *x,
 dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr,
                  int prec, int nrhs);
 
+/* dd_sap with the even-odd preconditioned block solve in place of plain MR
+ * (a standard refinement of the smoother; the paper's SAP is the plain form).
+ * With site parity (x+y+z+t) mod 2, A = (4+m0) + C site-local and H the
+ * in-block hops, each block solves D_BB delta = rho as
+ *   rhat_e = rho_e - H_eo A_oo^-1 rho_o,
+ *   nmr MR steps on S = A_ee - H_eo A_oo^-1 H_oe for S delta_e = rhat_e,
+ *   delta_o = A_oo^-1 (rho_o - H_oe delta_e).
+ * A_oo^-1 is applied through a Cholesky factor of each chiral half, formed on
+ * the device per mass.  Arguments, layout and errors as dd_sap. */
+dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr,
+                    int prec, int nrhs);
+
 /* Solve D x_r = b_r (r < nrhs) with FGMRES(m) preconditioned by SAP in
  * params->sap_prec, the Arnoldi basis, orthogonalisation, true residuals and
  * reductions in FP64 on the device.  b, x: canonical FP64 spinors (device
@@ -195,6 +208,7 @@ typedef struct {
     int ncy, nmr;            /* SAP cycles and MR steps (4, 4)                        */
     int sap_prec;            /* smoother precision (DD_F32)                           */
     int use_graphs;          /* replay captured hipGraphs for the Arnoldi step (1)    */
+    int sap_eo;              /* even-odd preconditioned block solves (0)              */
 } dd_server_config;
 
 typedef struct {

@@ -68,6 +68,7 @@ void dd_default_params(dd_params *p)
     p->ncy = 4;
     p->nmr = 4;
     p->sap_prec = DD_F32;
+    p->sap_eo = 0;
 }
 
 const char *dd_last_error(const dd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
@@ -275,6 +276,20 @@ dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int 
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
         return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec);
+    });
+}
+
+dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr, int prec, int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!m0 || !eta || !psi || eta == psi || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS || ncy < 0 || nmr < 0)
+        return fail(ctx, DD_INVALID_ARG, "dd_sap_eo: bad argument");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_sap_eo: no gauge field");
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap_eo: non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec, nullptr, true);
     });
 }
 

@@ -75,7 +75,7 @@ struct GeomHost {
 // launch as defined by the method (not the bytes the hardware moved).
 enum KClass {
     K_DSLASH_F64 = 0, K_DSLASH_F32IN_F64, K_DSLASH_F32, K_DSLASH_F16, K_DSLASH_BLOCK,
-    K_SAP_F64, K_SAP_F32, K_SAP_F16,
+    K_SAP_F64, K_SAP_F32, K_SAP_F16, K_SAP_EO_F64, K_SAP_EO_F32, K_SAP_EO_F16,
     K_CGS_DOTS, K_CGS_UPDATE, K_CGS_NORMALIZE, K_REDUCE, K_COMBINE, K_CONVERT, K_PACK,
     K_NCLASS
 };
@@ -164,8 +164,9 @@ struct SapSlots {
     const long *eta_off = nullptr;
     const long *psi_off = nullptr;
 };
+// eo selects the even-odd preconditioned block solve
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
-               const SapSlots *slots = nullptr);
+               const SapSlots *slots = nullptr, bool eo = false);
 
 // engine.hip
 Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,

@@ -18,6 +18,7 @@ struct EngineParams {
     int ncy = 4;
     int nmr = 4;
     int sap_prec = DD_F32;
+    bool sap_eo = false; // even-odd preconditioned block solves
     double tol = 1e-10;
     int max_restarts = 100;
     bool graphs = false; // capture the Arnoldi step as hipGraphs (needs a non-null stream)

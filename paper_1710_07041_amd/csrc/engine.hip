@@ -507,12 +507,12 @@ struct Engine::Impl {
         } else if (sap_prec == DD_F64) {
             ss.eta_off = d_eta_off();
             ss.psi_off = d_psi_off();
-            DD_TRY(run_sap(ctx, nullptr, W, V.p, Z.p, P.ncy, P.nmr, DD_F64, &ss));
+            DD_TRY(run_sap(ctx, nullptr, W, V.p, Z.p, P.ncy, P.nmr, DD_F64, &ss, P.sap_eo));
         } else if (sap_prec == DD_F32) {
             ss.psi_off = d_psi_off();
-            DD_TRY(run_sap(ctx, nullptr, W, lp.p, Z.p, P.ncy, P.nmr, DD_F32, &ss));
+            DD_TRY(run_sap(ctx, nullptr, W, lp.p, Z.p, P.ncy, P.nmr, DD_F32, &ss, P.sap_eo));
         } else {
-            DD_TRY(run_sap(ctx, nullptr, W, lp.p, sapout.p, P.ncy, P.nmr, DD_F16, &ss));
+            DD_TRY(run_sap(ctx, nullptr, W, lp.p, sapout.p, P.ncy, P.nmr, DD_F16, &ss, P.sap_eo));
             ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 12.0, 2.0 * vlen);
             k_unscale<<<grid(), TPB, 0, st()>>>(sapout.as<__half2>(), Z.as<float2>(), d_psi_off(), scl.as<double>(),
                                                 d_active(), ctx->g.nblocks, W);
@@ -905,6 +905,7 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
     ep.ncy = p.ncy;
     ep.nmr = p.nmr;
     ep.sap_prec = p.sap_prec;
+    ep.sap_eo = p.sap_eo != 0;
     ep.tol = p.tol;
     ep.max_restarts = p.max_restarts;
     ep.graphs = false;
@@ -941,12 +942,13 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
 
 void Engine::set_params(const EngineParams &p)
 {
-    // tolerance, restarts and smoother cycles may change between solves; the
+    // tolerance, restarts and the smoother's cycles and form may change between solves; the
     // shape (width, m, precision) may not
     d->P.tol = p.tol;
     d->P.max_restarts = p.max_restarts;
     d->P.ncy = p.ncy;
     d->P.nmr = p.nmr;
+    d->P.sap_eo = p.sap_eo;
     d->P.graphs = p.graphs;
     for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
     d->graphs.clear();

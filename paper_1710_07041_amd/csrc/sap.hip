@@ -178,18 +178,370 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     }
 }
 
+// ---------------------------------------------------------------------------
+// Even-odd preconditioned block solve (site parity p = (x+y+z+t) mod 2).  On
+// block B, with A = (4 + m0) + C site-local and H the in-block hops,
+//   S = A_ee - H_eo A_oo^-1 H_oe on the even sites,
+//   rhat_e = rho_e - H_eo A_oo^-1 rho_o,  nMR MR steps on S,
+//   delta_o = A_oo^-1 (rho_o - H_oe delta_e).
+// Threads 0-127 (waves 0-1) own the even sites, threads 128-255 (waves 2-3)
+// the odd ones, so every parity branch is uniform over a wavefront.  A hop
+// exchange between the parities is pipelined: at stage k the publishing
+// waves post direction k while the consuming waves take direction k-1 from
+// the other LDS buffer.  A_oo^-1 is applied through the Cholesky factor of
+// each chiral half (the halves are Hermitian positive definite: the clover
+// term is small against 4 + m0).
+// ---------------------------------------------------------------------------
+
+// Site of thread t: the pair {2k, 2k+1} (k = t mod 128) holds one even and
+// one odd site; which is which follows from (ly + lz + lt) mod 2.
+__device__ __forceinline__ int eo_site(int t)
+{
+    const int k = t & 127, odd = t >> 7;
+    const int bit = (((k >> 1) & 3) + ((k >> 3) & 3) + ((k >> 5) & 3)) & 1;
+    return 2 * k + (bit ^ odd);
+}
+
+// Slot of the upper entry (j, i), j < i, of a packed Hermitian 6x6 half.
+__host__ __device__ constexpr int hslot(int j, int i) { return 3 + j * 5 - j * (j - 1) / 2 + (i - j - 1); }
+
+// In place: the packed half c, plus diag on the diagonal, becomes its
+// Cholesky factor M = R^+ R (R upper triangular, real positive diagonal):
+// slots 0-2 receive 1/R_jj in pairs, the slot of (j, i) receives R_ji.
+template <typename A> __device__ __forceinline__ void chol_half(cx<A> c[18], A diag)
+{
+    A d[6] = {c[0].re + diag, c[0].im + diag, c[1].re + diag, c[1].im + diag, c[2].re + diag, c[2].im + diag};
+    A inv[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        A t = d[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            const cx<A> u = c[hslot(k, j)];
+            t -= u.re * u.re + u.im * u.im;
+        }
+        inv[j] = (A)1 / sqrt(t);
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            cx<A> acc = c[hslot(j, i)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) {
+                // acc -= conj(R_kj) R_ki
+                const cx<A> a = c[hslot(k, j)], b2 = c[hslot(k, i)];
+                acc.re -= a.re * b2.re + a.im * b2.im;
+                acc.im -= a.re * b2.im - a.im * b2.re;
+            }
+            c[hslot(j, i)] = inv[j] * acc;
+        }
+    }
+    c[0] = mk<A>(inv[0], inv[1]);
+    c[1] = mk<A>(inv[2], inv[3]);
+    c[2] = mk<A>(inv[4], inv[5]);
+}
+
+// x = M^-1 x in place from the factor written by chol_half: R^+ y = x, then
+// R x = y.
+template <typename A> __device__ __forceinline__ void chol_solve(const cx<A> f[18], cx<A> x[6])
+{
+    const A inv[6] = {f[0].re, f[0].im, f[1].re, f[1].im, f[2].re, f[2].im};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        cx<A> acc = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            // acc -= conj(R_ki) y_k
+            const cx<A> a = f[hslot(k, i)];
+            acc.re -= a.re * x[k].re + a.im * x[k].im;
+            acc.im -= a.re * x[k].im - a.im * x[k].re;
+        }
+        x[i] = inv[i] * acc;
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        cx<A> acc = x[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) acc = acc - f[hslot(i, k)] * x[k];
+        x[i] = inv[i] * acc;
+    }
+}
+
+// LDS of the even-odd sweep.  The residual on entry uses the plain block
+// exchange (all 256 sites post); the parity exchanges post only one parity
+// at a time, so their buffers are indexed by the ordinal k = s / 2 of the
+// posting site and share the memory of the full exchange, next to rho of
+// the odd sites.
+template <typename A> struct EoLds {
+    cx<A> hf[2][6][BS / 2];
+    cx<A> hb[2][6][BS / 2];
+    cx<A> rho[12][BS / 2]; // rho of the odd sites
+};
+template <typename A> union SapEoShared {
+    Lds<A> full;
+    EoLds<A> eo;
+};
+
+// Post direction MU of v (this thread's site s) into buffer X.
+template <int MU, typename A>
+__device__ __forceinline__ void eo_publish(EoLds<A> &L, int X, int s, const cx<A> U[9], const cx<A> v[12])
+{
+    cx<A> h[6], t[6];
+    const int k = s >> 1;
+    proj_minus<MU>(v, h);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.hf[X][c][k] = h[c];
+    proj_plus<MU>(v, h);
+    su3_mul_adj(U, h, t);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.hb[X][c][k] = t[c];
+}
+
+// Take direction MU from buffer X: q += the two in-block hops of site s.
+template <int MU, typename A>
+__device__ __forceinline__ void eo_consume(EoLds<A> &L, int X, const Geom &g, int b, const int bc[4], int s,
+                                           const cx<A> U[9], cx<A> q[12])
+{
+    const bool wraps = g.nb[MU] == 1; // uniform
+    cx<A> h[6], t[6];
+    int bn, sn, sign;
+    bool inb;
+    neighbour<MU, +1>(g, b, bc, s, bn, sn, sign, inb);
+    if (inb) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) h[c] = L.hf[X][c][sn >> 1];
+        su3_mul(U, h, t);
+        if (wraps) recon_minus<MU>(q, t, (A)sign);
+        else recon_minus1<MU>(q, t);
+    }
+    neighbour<MU, -1>(g, b, bc, s, bn, sn, sign, inb);
+    if (inb) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = L.hb[X][c][sn >> 1];
+        if (wraps) recon_plus<MU>(q, t, (A)sign);
+        else recon_plus1<MU>(q, t);
+    }
+}
+
+// q += H v across the parities: the waves with pub set post v, the others
+// accumulate the hops into q.  Stage k posts direction k and takes direction
+// k - 1 (the two LDS buffers alternate), one barrier per stage.  Buffer reuse
+// is safe across consecutive calls: a buffer is rewritten only after a
+// barrier that follows its last read.
+template <typename A>
+__device__ __forceinline__ void eo_exchange(EoLds<A> &L, const Geom &g, int b, const int bc[4], int s,
+                                            const cx<A> Ur[4][9], bool pub, const cx<A> v[12], cx<A> q[12])
+{
+    if (pub) eo_publish<0, A>(L, 0, s, Ur[0], v);
+    __syncthreads();
+    if (pub) eo_publish<1, A>(L, 1, s, Ur[1], v);
+    else eo_consume<0, A>(L, 0, g, b, bc, s, Ur[0], q);
+    __syncthreads();
+    if (pub) eo_publish<2, A>(L, 0, s, Ur[2], v);
+    else eo_consume<1, A>(L, 1, g, b, bc, s, Ur[1], q);
+    __syncthreads();
+    if (pub) eo_publish<3, A>(L, 1, s, Ur[3], v);
+    else eo_consume<2, A>(L, 0, g, b, bc, s, Ur[2], q);
+    __syncthreads();
+    if (!pub) eo_consume<3, A>(L, 1, g, b, bc, s, Ur[3], q);
+}
+
+// x = M^-1 x in place with the factor of chiral half 1 held in LDS.
+template <typename A> __device__ __forceinline__ void chol_solve_lds(const cx<A> (*F)[BS / 2], int k, cx<A> x[6])
+{
+    cx<A> f[18];
+#pragma unroll
+    for (int e = 0; e < 18; ++e) f[e] = F[e][k];
+    chol_solve<A>(f, x);
+}
+
 template <typename S, typename A, typename RES>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep_eo(
+    const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
+    const vec2_t<S> *__restrict__ clov, SArgs a)
+{
+    static_assert(RES::links && RES::clover_half, "even-odd sweep: links and clover half 0 in registers");
+    __shared__ SapEoShared<A> SH;
+    __shared__ cx<A> Dd[12][BS / 2]; // delta_e of the even sites (by even ordinal)
+    __shared__ cx<A> F1[18][BS / 2]; // Cholesky factor of chiral half 1 of the odd sites
+    Lds<A> &L = SH.full;
+    EoLds<A> &E = SH.eo;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = a.blocks[i];
+    const int tid = threadIdx.x, s = eo_site(tid), k = tid & (BS / 2 - 1);
+    const bool odd = tid >= BS / 2; // uniform over a wavefront
+    const int lane = tid & 63, wave = tid >> 6;
+    int bc[4];
+    block_coords(a.g, b, bc);
+
+    // register-resident links carry the hop factor -1/2
+    cx<A> U[4][9];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc_stream<A>(u + e * BS);
+    }
+    const vec2_t<S> *cp0 = clov + (long)b * 36 * BS + s;
+
+    for (int r = 0; r < a.nrhs; ++r) {
+        const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
+        const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
+        vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
+        const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
+        // clover half 0 (odd sites factor it in place below, so it is
+        // reloaded for every right-hand side)
+        cx<A> cl[18];
+#pragma unroll
+        for (int e = 0; e < 18; ++e) cl[e] = ldc<A>(cp0 + e * BS);
+        if (odd) {
+            // factor of chiral half 1 of A_oo = (4 + m0) + C, kept in LDS
+            cx<A> c1[18];
+#pragma unroll
+            for (int e = 0; e < 18; ++e) c1[e] = ldc<A>(cp0 + (18 + e) * BS);
+            chol_half<A>(c1, diag);
+#pragma unroll
+            for (int e = 0; e < 18; ++e) F1[e][k] = c1[e];
+        }
+
+        // rho = eta - (D psi)_B
+        cx<A> rho[12], q[12];
+        {
+            cx<A> p0[12];
+            if (a.mode == 2) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) p0[c] = ldc<A>(psi + sp + c * BS);
+                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, p0, q);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+            }
+        }
+        if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rho[c] = ldc_stream<A>(eta + sp + c * BS) - q[c];
+        // the parity exchanges reuse the memory of the full one
+        __syncthreads();
+
+        // Two vectors per thread from here on: r (even sites) and q.  In each
+        // parity exchange the posting waves read q or r and the receiving
+        // waves accumulate into q, so one array serves both roles.
+        cx<A> rr[12];
+        if (odd) {
+            // rho_o to LDS; factor chiral half 0 in place; q = A_oo^-1 rho_o
+#pragma unroll
+            for (int c = 0; c < 12; ++c) E.rho[c][k] = rho[c];
+            chol_half<A>(cl, diag);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[c] = rho[c];
+            chol_solve<A>(cl, q);
+            chol_solve_lds<A>(F1, k, q + 6);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = mk<A>(0, 0);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                rr[c] = rho[c];
+                q[c] = mk<A>(0, 0);
+                Dd[c][k] = mk<A>(0, 0);
+            }
+        }
+        // even: r_e = rho_e - H_eo A_oo^-1 rho_o
+        eo_exchange<A>(E, a.g, b, bc, s, U, odd, q, q);
+        if (!odd) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = rr[c] - q[c];
+        }
+
+        // MR on S = A_ee - H_eo A_oo^-1 H_oe
+        for (int it = 0; it < a.nmr; ++it) {
+            // odd: q = H_oe r_e
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+            eo_exchange<A>(E, a.g, b, bc, s, U, !odd, rr, q);
+            if (odd) {
+                // q = -A_oo^-1 H_oe r_e
+                chol_solve<A>(cl, q);
+                chol_solve_lds<A>(F1, k, q + 6);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = mk<A>(-q[c].re, -q[c].im);
+            } else {
+                // q = A_ee r_e
+                clover_half_mac<A>(cl, diag, rr, q);
+                cx<A> c2[18];
+                const vec2_t<S> *cp1 = cp0 + 18 * BS;
+                // the same address at every MR step: hide that, or the loads
+                // leave the loop and the half is held in registers
+                asm volatile("" : "+v"(cp1));
+#pragma unroll
+                for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp1 + e * BS);
+                clover_half_mac<A>(c2, diag, rr + 6, q + 6);
+            }
+            // even: q = A_ee r_e - H_eo A_oo^-1 H_oe r_e = S r_e
+            eo_exchange<A>(E, a.g, b, bc, s, U, odd, q, q);
+            if (odd) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+            }
+            cx<A> alpha;
+            if (!mr_alpha(L, lane, wave, q, rr, alpha)) break;
+            if (!odd) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    cx<A> d = Dd[c][k];
+                    cmac(d, alpha, rr[c]);
+                    Dd[c][k] = d;
+                    rr[c] = rr[c] - alpha * q[c];
+                }
+            }
+        }
+
+        // odd: delta_o = A_oo^-1 (rho_o - H_oe delta_e); even: delta_e
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            rr[c] = odd ? mk<A>(0, 0) : Dd[c][k];
+            q[c] = mk<A>(0, 0);
+        }
+        eo_exchange<A>(E, a.g, b, bc, s, U, !odd, rr, q);
+        if (odd) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = E.rho[c][k] - q[c];
+            chol_solve<A>(cl, rr);
+            chol_solve_lds<A>(F1, k, rr + 6);
+        }
+        // psi_B += delta_B
+        if (a.mode == 2) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = rr[c] + ldc<A>(psi + sp + c * BS);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, rr[c]);
+        // the next right-hand side's residual reuses the LDS read above
+        __syncthreads();
+    }
+}
+
+template <typename S, typename A, typename RES, bool EO>
 Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 {
     // algorithmic traffic of one colour sweep: links + clover once, eta, psi
     // (read only when nonzero) and psi written, per swept site and rhs
     const double sites = 256.0 * a.nblk, sb = (double)sizeof(S), n = a.nrhs;
     const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0)));
-    const double fl = sites * n * (a.nmr * 2184.0 + (a.mode == 2 ? 1848.0 : 0.0));
-    ProfScope ps(ctx->prof, ctx->stream, prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16, by, fl);
-    k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
-        static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
-        static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p), a);
+    // the even-odd form adds one in-block hop application (the right-hand
+    // side and the odd reconstruction) per block solve
+    const double fl = sites * n * (a.nmr * 2184.0 + (a.mode == 2 ? 1848.0 : 0.0) + (EO ? 1848.0 : 0.0));
+    const int cls = EO ? (prec == DD_F64 ? K_SAP_EO_F64 : prec == DD_F32 ? K_SAP_EO_F32 : K_SAP_EO_F16)
+                       : (prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16);
+    ProfScope ps(ctx->prof, ctx->stream, cls, by, fl);
+    if constexpr (EO)
+        k_sap_sweep_eo<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
+            static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
+            static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
+            a);
+    else
+        k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
+            static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
+            static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
+            a);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
@@ -201,11 +553,14 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
 typedef Residency<true, false, 2, true> ResF32;
 typedef Residency<true, false, 2, true> ResF16;
 typedef Residency<true, false, 1, true> ResF64;
+// The even-odd sweep holds more per thread (two vectors, the factor or the
+// clover, the four links) and runs at one wavefront per SIMD.
+typedef Residency<true, false, 1, true> ResEO;
 
 } // namespace
 
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
-               const SapSlots *slots)
+               const SapSlots *slots, bool eo)
 {
     if (!eta || !psi || !ctx->links[prec].p || !ctx->clover[prec].p || (!m0 && !(slots && slots->m0_dev)))
         return Status{DD_INVALID_ARG, "SAP: missing buffer"};
@@ -235,9 +590,15 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
             a.blocks = ctx->colour_blocks[col].as<int>();
             a.nblk = ctx->ncolour[col];
             a.mode = (cy == 0 && col == 0) ? 0 : (cy == 0 ? 1 : 2);
-            if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64>(ctx, a, prec, eta, psi)));
-            else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32>(ctx, a, prec, eta, psi)));
-            else DD_TRY((sweep<__half, float, ResF16>(ctx, a, prec, eta, psi)));
+            if (eo) {
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi)));
+                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi)));
+            } else {
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi)));
+                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi)));
+            }
         }
     return Status::ok();
 }

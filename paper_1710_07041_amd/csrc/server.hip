@@ -233,6 +233,7 @@ void dd_server_default_config(dd_server_config *c)
     c->ncy = 4;
     c->nmr = 4;
     c->sap_prec = DD_F32;
+    c->sap_eo = 0;
     c->use_graphs = 1;
 }
 
@@ -305,6 +306,7 @@ dd_status dd_server_add_field(dd_server *s, const int dims[4], const int bcs[4],
     ep.ncy = s->cfg.ncy;
     ep.nmr = s->cfg.nmr;
     ep.sap_prec = s->cfg.sap_prec;
+    ep.sap_eo = s->cfg.sap_eo != 0;
     ep.tol = s->cfg.tol;
     ep.max_restarts = s->cfg.max_restarts;
     ep.graphs = s->cfg.use_graphs != 0;

@@ -38,7 +38,7 @@ DD_MAX_RHS = 16
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
-    "dd_apply_D_block", "dd_sap", "dd_solve", "dd_profile_enable", "dd_profile_read",
+    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_profile_enable", "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
     "dd_server_destroy",
@@ -47,7 +47,7 @@ EXPORTS = [
 
 class dd_params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
-                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int)]
+                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("sap_eo", ctypes.c_int)]
 
 
 class dd_solve_info(ctypes.Structure):
@@ -63,7 +63,8 @@ class dd_kernel_stat(ctypes.Structure):
 class dd_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_width", ctypes.c_int), ("m", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int), ("ncy", ctypes.c_int),
-                ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("sap_eo", ctypes.c_int)]
 
 
 class dd_server_stats(ctypes.Structure):
@@ -91,6 +92,7 @@ _sigs = {
     "dd_apply_D": ([_vp, _dp, _vp, _vp, _i, _i], _i),
     "dd_apply_D_block": ([_vp, _d, _l, _vp, _vp, _i], _i),
     "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
+    "dd_sap_eo": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
     "dd_profile_enable": ([_vp, _i], _i),
     "dd_server_default_config": ([ctypes.POINTER(dd_server_config)], None),
@@ -212,10 +214,12 @@ class Context:
         self._check(_lib.dd_apply_D_block(self._h, float(m0), int(block_id), _vp(_ptr(x)), _vp(_ptr(y)),
                                           PREC.get(prec, prec)))
 
-    def sap(self, m0, eta, psi, ncy, nmr, prec, nrhs=1):
+    def sap(self, m0, eta, psi, ncy, nmr, prec, nrhs=1, eo=False):
+        """dd_sap, or dd_sap_eo (even-odd block solves) when eo is set."""
         _, mp = _masses(m0, nrhs)
-        self._check(_lib.dd_sap(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), int(ncy), int(nmr),
-                                PREC.get(prec, prec), int(nrhs)))
+        fn = _lib.dd_sap_eo if eo else _lib.dd_sap
+        self._check(fn(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), int(ncy), int(nmr), PREC.get(prec, prec),
+                       int(nrhs)))
 
     def solve(self, m0, b, x, nrhs=1, params: dd_params | None = None, raise_on_fail=True):
         """b, x: canonical complex128 device tensors (nrhs, V, 4, 3); x holds x0."""

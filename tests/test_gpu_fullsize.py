@@ -86,6 +86,22 @@ def test_c2_mixed_solve_oracle_residual(c2, c2_clover):
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
 
 
+def test_c2_mixed_solve_eo_oracle_residual(c2, c2_clover):
+    """The same solve with the even-odd preconditioned smoother (dd_sap_eo)."""
+    import torch
+    from paper_1710_07041_amd import ddsap
+    b = synth.gaussian_spinor(c2.dims, seed=0)
+    bd = to_dev(b)[None]
+    xd = torch.zeros_like(bd)
+    p = ddsap.default_params()
+    p.sap_eo = 1
+    st, info = c2.ctx.solve(-0.35, bd, xd, 1, p)
+    assert st == ddsap.DD_OK
+    x = to_host(xd)[0]
+    r = b - oracle.apply_D(c2.dims, c2.U, c2_clover, -0.35, x, BC)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
 def test_c4_point_sources_oracle_residual(c2, c2_clover):
     """Twelve spin-colour point sources solved fused; each residual <= 1e-10 by the oracle."""
     import torch
