@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-steps", type=int, default=1, help="FP64-smoother solves timed alongside")
+    ap.add_argument("--eo-steps", type=int, default=1,
+                    help="solves with the even-odd preconditioned smoother (mixed and FP64) timed alongside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--serve", action="store_true", help="run the continuous-batching serving workload instead")
@@ -268,14 +270,15 @@ def main():
     xd = torch.zeros_like(bd)
     m0 = np.full(nrhs, w["m0"])
 
-    def params(sap):
+    def params(sap, eo=False):
         p = ddsap.default_params()
         p.sap_prec = ddsap.PREC[sap]
+        p.sap_eo = int(eo)
         return p
 
-    def one_solve(sap):
+    def one_solve(sap, eo=False):
         xd.zero_()
-        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap), raise_on_fail=False)
+        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap, eo), raise_on_fail=False)
         if st != ddsap.DD_OK:
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
@@ -315,6 +318,31 @@ def main():
         torch.cuda.synchronize()
         t64 = (time.perf_counter() - t0) / args.fp64_steps
         log(f"fp64 path: {info64[0]['iterations']} iterations, {t64 * 1e3:.1f} ms")
+
+    # the even-odd preconditioned smoother (a refinement beyond the paper's
+    # plain block MR), mixed and FP64, timed alongside
+    even_odd = None
+    if args.eo_steps > 0:
+        even_odd = {}
+        for sap in (w["sap"], "f64"):
+            one_solve(sap, eo=True)
+            ctx.profile_enable(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.eo_steps):
+                info_eo = one_solve(sap, eo=True)
+            torch.cuda.synchronize()
+            t_eo = (time.perf_counter() - t0) / args.eo_steps
+            prof_eo = ctx.profile_read()
+            ctx.profile_enable(False)
+            cls = f"sap_sweep_eo_{sap}"
+            sweep = prof_eo.get(cls)
+            even_odd["mixed" if sap != "f64" else "fp64"] = {
+                "time_s": round(t_eo, 4), "iterations": info_eo[0]["iterations"],
+                "rel_residual": max(i["rel_residual"] for i in info_eo),
+                "sweep_avg_ms": None if not sweep else round(sweep["total_ms"] / sweep["launches"], 4)}
+            log(f"even-odd smoother {sap}: {info_eo[0]['iterations']} iterations, {t_eo * 1e3:.1f} ms")
+        even_odd["mixed_speedup_over_plain"] = round(t_mixed / even_odd["mixed"]["time_s"], 3)
 
     # multi-RHS: the same right-hand sides solved one at a time, for the fusion gain
     sequential = None
@@ -405,6 +433,7 @@ def main():
             "speedup": round(sequential / t_mixed, 3)},
         "iterations": {"mixed": infos[-1][0]["iterations"],
                        "fp64": None if info64 is None else info64[0]["iterations"]},
+        "even_odd": even_odd,
         "final_rel_residual": max(i["rel_residual"] for i in infos[-1]),
         "kernels": breakdown,
         "cpu_baseline": cpu,
