@@ -7,8 +7,10 @@
 // One launch sweeps every block of one colour.  One 256-thread workgroup owns
 // one 4^4 block, one thread one site, and keeps everything the MR loop needs
 // on chip:
-//   * the site's four forward links (and, below FP64, its clover term) live
-//     in registers for the whole sweep and every right-hand side;
+//   * the site's four forward links (pre-multiplied by the hop factor -1/2)
+//     and chiral half 0 of its clover term live in registers for the whole
+//     sweep and every right-hand side; clover half 1 is re-read at each block
+//     application and stays in L2; the MR accumulator lives in LDS;
 //   * D_BB is applied direction by direction: each thread publishes the
 //     spin-projected half spinor of its site for the +mu hop of site x-mu and
 //     U_mu(x)^+ times the projected half spinor for the -mu hop of site x+mu
@@ -20,6 +22,10 @@
 // other colour's psi (and, for -mu hops, the neighbour's link) from memory.
 // Blocks of one colour share no site and read only the other colour's psi,
 // so a sweep needs no synchronisation between workgroups.
+//
+// k_sap_sweep_eo is the same sweep with the even-odd preconditioned block
+// solve (MR on the even-site Schur complement, odd sites reconstructed);
+// see the comment above it.
 #include "block_ops.h"
 #include "dd_device.h"
 #include "dd_internal.h"
