@@ -17,6 +17,10 @@
 //     through LDS, so no spinor leaves the chip inside the MR loop;
 //   * the two block dot products per MR step reduce with wavefront shuffles
 //     and a fixed-order combine of the four wavefronts (deterministic).
+// eta and psi go through the caches (they are re-read by the next sweep and
+// by the operator that follows the smoother, and fit in the 256 MB
+// last-level cache in FP32); links and clover half 0, read once per sweep,
+// stream.
 // The block residual eta_B - (D psi)_B is formed on entry: the in-block part
 // by the same LDS exchange, the hops that leave the block by reading the
 // other colour's psi (and, for -mu hops, the neighbour's link) from memory.
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
             cx<A> d0[12];
             if (a.mode == 2) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) d0[c] = ldc_stream<A>(psi + sp + c * BS);
+                for (int c = 0; c < 12; ++c) d0[c] = ldc<A>(psi + sp + c * BS);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) d0[c] = mk<A>(0, 0);
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         if (a.mode != 0) face_hops<S, S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
         // rho = eta - (D psi)_B
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rr[c] = ldc_stream<A>(eta + sp + c * BS) - q[c];
+        for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(eta + sp + c * BS) - q[c];
         // MR on D_BB
         for (int it = 0; it < a.nmr; ++it) {
             block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
@@ -176,10 +180,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         }
         if constexpr (RES::clover_half) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, D.d[c][s]);
+            for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, D.d[c][s]);
         } else {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, del[c]);
+            for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, del[c]);
         }
     }
 }
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         }
         if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rho[c] = ldc_stream<A>(eta + sp + c * BS) - q[c];
+        for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(eta + sp + c * BS) - q[c];
         // the parity exchanges reuse the memory of the full one
         __syncthreads();
 
@@ -519,7 +523,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
             for (int c = 0; c < 12; ++c) rr[c] = rr[c] + ldc<A>(psi + sp + c * BS);
         }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc_stream(psi + sp + c * BS, rr[c]);
+        for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, rr[c]);
         // the next right-hand side's residual reuses the LDS read above
         __syncthreads();
     }
