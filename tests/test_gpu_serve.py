@@ -25,7 +25,7 @@ def fields():
     return out
 
 
-def solo(dims, U, m0, b, sap="f32"):
+def solo(dims, U, m0, b, sap="f32", eo=0):
     import torch
     from paper_1710_07041_amd import ddsap
     ctx = ddsap.Context(dims, BC)
@@ -34,6 +34,7 @@ def solo(dims, U, m0, b, sap="f32"):
     xd = torch.zeros_like(bd)
     p = ddsap.default_params()
     p.sap_prec = ddsap.PREC[sap]
+    p.sap_eo = eo
     st, info = ctx.solve(m0, bd, xd, b.shape[0], p)
     ctx.close()
     return to_host(xd)
@@ -52,11 +53,11 @@ def make_requests(fields, n, seed=0):
     return reqs
 
 
-@pytest.mark.parametrize("graphs", [1, 0])
-def test_serve_mix_equals_alone(fields, graphs):
+@pytest.mark.parametrize("graphs,eo", [(1, 0), (0, 0), (1, 1)], ids=["graphs", "nographs", "graphs-evenodd"])
+def test_serve_mix_equals_alone(fields, graphs, eo):
     import torch
     from paper_1710_07041_amd import ddsap
-    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30)
+    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30, sap_eo=eo)
     fids = [srv.add_field(dims, U, 1.0, BC) for dims, U, _ in fields]
     for f in fids:
         assert srv.field_info(f)[0] == 3
@@ -84,7 +85,7 @@ def test_serve_mix_equals_alone(fields, graphs):
         for r in range(b.shape[0]):
             res = b[r] - oracle.apply_D(dims, U, C, m0[r], x[r], BC)
             assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10
-        xs = solo(dims, U, m0, b)
+        xs = solo(dims, U, m0, b, eo=eo)
         assert rel(x, xs) <= 1e-8
 
 
