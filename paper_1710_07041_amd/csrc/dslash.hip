@@ -3,13 +3,18 @@
 //   (D psi)(x) = (4 + m0) psi(x) + C(x) psi(x)
 //              - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
 //
-// One thread per (site, right-hand side); one 256-thread workgroup per
-// (Schwarz block, right-hand side).  The hop uses the chiral-basis spin
-// projection so each of the eight SU(3) products acts on two spins only.
+// Gather form (k_dslash): one thread per site, one 256-thread workgroup per
+// (Schwarz block, group of RT right-hand sides); the RT right-hand sides of a
+// thread share every link and clover load.  The hop uses the chiral-basis
+// spin projection so each of the eight SU(3) products acts on two spins only.
+// Block-wise form (k_dslash_lds, FP32 fields with many right-hand sides):
+// links and clover in registers for all right-hand sides, in-block hops
+// through the LDS exchange of the smoother.
 // Bandwidth bound: per site the algorithmic traffic is links 72 + clover 72 +
-// spinor in 24 + out 24 reals.  Workgroups are remapped so that each XCD
-// sweeps a contiguous range of blocks (shared L2 for the neighbour faces);
-// clover terms and outputs, used once, go through streaming loads/stores.
+// spinor in 24 + out 24 reals per right-hand side.  Workgroups are remapped
+// so that each XCD sweeps a contiguous range of blocks (shared L2 for the
+// neighbour faces); clover terms and outputs, used once, go through
+// streaming loads/stores.
 #include "block_ops.h"
 #include "dd_device.h"
 #include "dd_internal.h"
@@ -106,9 +111,11 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
                                      cx<A> acc[RT][12])
 {
     if constexpr (PAIR && !BLOCKONLY && RT == 1 && sizeof(SI) <= 4) {
-        // FP32 input: both hops of a direction in one trip, so the link that
-        // site x - mu reads for its forward hop is re-read for the backward
-        // hop of site x at once (from L1) rather than a trip later
+        // FP32 or FP16 input, one right-hand side: both hops of a direction
+        // in one trip, so the link that site x - mu reads for its forward hop
+        // is re-read for the backward hop of site x at once (from L1) rather
+        // than a trip later (with FP64 input the pair does not fit in
+        // registers; that form loads the next hop's link one trip ahead)
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             int bf, sf, gf, bb, sb, gb;
