@@ -20,7 +20,7 @@ from collections import defaultdict
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
-KERNEL_SOURCES = ["csrc/sap.hip", "csrc/dslash.hip", "csrc/dd_device.h", "csrc/engine.hip"]
+KERNEL_SOURCES = ["csrc/sap.hip", "csrc/dslash.hip", "csrc/dd_device.h", "csrc/block_ops.h", "csrc/engine.hip"]
 COPY_BYTES = 1 << 30
 
 CLASS_PATTERNS = [
@@ -37,10 +37,18 @@ CLASS_PATTERNS = [
 ]
 
 
+def _code_only(text: str) -> str:
+    """The source without // comments, /* */ comments and blank lines, so a
+    comment edit does not invalidate a measurement."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        h.update((PKG / rel).read_bytes())
+        h.update(_code_only((PKG / rel).read_text()).encode())
     return h.hexdigest()[:16]
 
 
