@@ -172,7 +172,10 @@ dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int 
  *   nmr MR steps on S = A_ee - H_eo A_oo^-1 H_oe for S delta_e = rhat_e,
  *   delta_o = A_oo^-1 (rho_o - H_oe delta_e).
  * A_oo^-1 is applied through a Cholesky factor of each chiral half, formed on
- * the device per mass.  Arguments, layout and errors as dd_sap. */
+ * the device per mass; this needs (4+m0) + C positive definite on every
+ * chiral half (true whenever 4+m0 exceeds the clover term's norm, as for all
+ * physical masses), otherwise psi holds NaN.  Arguments, layout and errors as
+ * dd_sap. */
 dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr,
                     int prec, int nrhs);
 
