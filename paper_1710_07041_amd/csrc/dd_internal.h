@@ -151,9 +151,11 @@ Status any_nonfinite(dd_ctx *ctx, const double *p, size_t n, bool &bad);
 // from out_prec only for (F32 in, F64 out) and (F64 in, F64 out).  Masses
 // come from the host array m0 or, when m0_dev is set, from device memory;
 // in_off (device, nullable) adds a per-rhs element offset to the input.
+// active (device, nullable): right-hand sides with active[r] == 0 are skipped
+// (their output is left as it was).
 Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
                      int field_prec, const double *resid, const double *m0_dev = nullptr,
-                     const long *in_off = nullptr);
+                     const long *in_off = nullptr, const int *active = nullptr);
 Status launch_dslash_block(dd_ctx *ctx, double m0, int block_id, const void *in, void *out, int prec);
 
 // sap.hip
@@ -163,6 +165,7 @@ struct SapSlots {
     const double *m0_dev = nullptr;
     const long *eta_off = nullptr;
     const long *psi_off = nullptr;
+    const int *active = nullptr; // slots with active[r] == 0 are skipped (psi left as it was)
 };
 // eo selects the even-odd preconditioned block solve
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,

@@ -31,6 +31,7 @@ struct DArgs {
     double m0[MAXRHS];
     const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
     const long *in_off;   // per-rhs element offset added to the input (nullable)
+    const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
 };
 
 // One hop of direction index k = 2 mu + (0: forward, 1: backward) onto acc.
@@ -214,6 +215,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         const int wg = xcd_remap(blockIdx.x, gridDim.x);
         b = wg / a.ngroups;
         r0 = (wg - b * a.ngroups) * RT;
+        if (RT == 1 && a.active && !a.active[r0]) return; // uniform over the workgroup
     }
     const int nr = a.nrhs - r0 < RT ? a.nrhs - r0 : RT;
     const int s = threadIdx.x;
@@ -307,6 +309,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         for (int e = 0; e < (RES::clover ? 36 : 1); ++e) cl[e] = ldc<A>(cp + e * BS);
     }
     for (int r = 0; r < a.nrhs; ++r) {
+        if (a.active && !a.active[r]) continue; // uniform over the workgroup
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
         const vec2_t<SI> *__restrict__ inr = in + (a.in_off ? a.in_off[r] : 0);
         const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
@@ -400,13 +403,14 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
 } // namespace
 
 Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, int in_prec, void *out, int out_prec,
-                     int field_prec, const double *resid, const double *m0_dev, const long *in_off)
+                     int field_prec, const double *resid, const double *m0_dev, const long *in_off, const int *active)
 {
     if (!in || !out || !ctx->links[field_prec].p || !ctx->clover[field_prec].p || (!m0 && !m0_dev))
         return Status{DD_INVALID_ARG, "operator: missing buffer"};
     DArgs a = make_args(ctx, m0, nrhs);
     a.m0_dev = m0_dev;
     a.in_off = in_off;
+    a.active = active;
     bool rs = resid != nullptr;
     if (in_prec == DD_F64 && out_prec == DD_F64 && field_prec == DD_F64)
         return rs ? launch<double, double, double, double, true>(ctx, a, in, out, DD_F64, resid)

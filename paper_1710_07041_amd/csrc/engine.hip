@@ -494,6 +494,7 @@ struct Engine::Impl {
     {
         SapSlots ss;
         ss.m0_dev = d_m0();
+        ss.active = d_active(); // done or empty slots cost no smoother work
         if (P.ncy == 0) {
             // no smoother: z_j = v_j (the smoother-precision copy, or V itself in FP64)
             ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 2 * 2 * real_bytes(zprec), 0.0);
@@ -518,7 +519,7 @@ struct Engine::Impl {
                                                 d_active(), ctx->g.nblocks, W);
             DD_HIP_TRY(hipGetLastError());
         }
-        DD_TRY(launch_dslash(ctx, nullptr, W, Z.p, zprec, w.p, DD_F64, DD_F64, nullptr, d_m0(), d_in_off()));
+        DD_TRY(launch_dslash(ctx, nullptr, W, Z.p, zprec, w.p, DD_F64, DD_F64, nullptr, d_m0(), d_in_off(), d_active()));
         DD_TRY(dots(w.as<double2>(), nvmax));
         DD_TRY(reduce(res.as<double2>()));
         DD_TRY(update_dots(w.as<double2>(), nvmax, res.as<double2>()));

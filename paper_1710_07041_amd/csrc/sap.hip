@@ -49,6 +49,7 @@ struct SArgs {
     const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
     const long *eta_off;  // per-rhs element offsets of eta and psi (nullable)
     const long *psi_off;
+    const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
 };
 
 // The MR coefficient of one right-hand side: the dot products <q, r> and
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     }
 
     for (int r = 0; r < a.nrhs; ++r) {
+        if (a.active && !a.active[r]) continue; // uniform over the workgroup
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
         const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
         vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     const vec2_t<S> *cp0 = clov + (long)b * 36 * BS + s;
 
     for (int r = 0; r < a.nrhs; ++r) {
+        if (a.active && !a.active[r]) continue; // uniform over the workgroup
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
         const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
         vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
@@ -593,6 +596,7 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
         a.m0_dev = slots->m0_dev;
         a.eta_off = slots->eta_off;
         a.psi_off = slots->psi_off;
+        a.active = slots->active;
     }
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
