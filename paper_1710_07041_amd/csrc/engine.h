@@ -32,8 +32,16 @@ struct SlotState {
     int cycle_len = 0; // length of a cycle that just ended (combine pending)
     bool need_bnorm = false;
     double bnorm = 0, m0 = 0;
-    std::vector<std::complex<double>> H, g, sn;
+    double beta0 = 0;     // |r| at the start of the cycle
+    double beta_prev = 0; // last subdiagonal entry, against the not yet reorthogonalised p_j
+    // H: unrotated Hessenberg matrix ((m+1) x m, row stride m); R, g, cs, sn:
+    // its Givens QR and the rotated right-hand side, rebuilt by qr()
+    std::vector<std::complex<double>> H, R, g, sn;
     std::vector<double> cs;
+    // QR of the leading (n+1) x n block; returns the residual estimate |g[n]|
+    double qr(int m, int n);
+    // y = R^-1 g over n columns (ENGINE_MAXM entries, the rest zero)
+    void solve_y(int m, int n, std::complex<double> *y) const;
     dd_solve_info info{};
     long owner = 0; // caller's tag (request id) and right-hand-side index
     int owner_rhs = 0;

@@ -15,11 +15,24 @@
 //                              smoother writes straight into slot r's Z[j_r])
 //   w     = D z_j             (FP64 operator reading the stored z_j, so the
 //                              Arnoldi relation D Z = V H holds exactly)
-//   CGS2  in three fused passes over V, each slot with its own j_r:
-//     (1) h1 = V^+ w
-//     (2) w' = w - V h1, h2 = V^+ w', |w'|^2, max|w'|
-//     (3) w'' = w' - V h2, v_{j+1} = w''/h, smoother-precision copy,
-//         h^2 = |w'|^2 - |h2|^2
+//   CGS2 with the reorthogonalisation of v_j delayed into step j+1 (the
+//   low-synchronisation "DCGS2" arrangement: Swirydowicz, Langou, Ananthan,
+//   Yang, Thomas, Numer. Linear Algebra Appl. 28 (2021) e2343), two passes
+//   over V per step instead of three.  V[j] holds p_j, the once-orthogonalised
+//   and normalised vector of the previous step, and V[0..j-1] the final basis:
+//     (A) c = V[0..j-1]^+ p_j, |p_j|^2, s = V[0..j-1]^+ w, <p_j, w>, |w|^2
+//     (B) v_j = (p_j - V c)/alpha (written over p_j),
+//         w'  = w - V[0..j-1] s - h_jj v_j,  p_{j+1} = w'/beta,
+//         smoother-precision copy of p_{j+1}
+//   with alpha^2 = |p_j|^2 - |c|^2, h_jj = (<p_j, w> - c^+ s)/alpha and
+//   beta^2 = |w|^2 - |s|^2 - |h_jj|^2.  Since p_j = V c + alpha v_j, the
+//   Hessenberg column j-1 (whose last entry was beta_{j-1} against p_j) is
+//   finished at step j: h_{i,j-1} += beta_{j-1} c_i, h_{j,j-1} = beta_{j-1}
+//   alpha.  The stopping estimate of step j uses column j as it stands; its
+//   correction is of the size of the rounding error of once-orthogonalised
+//   Gram-Schmidt and only the FP64 true residual stops a slot.  The smoother
+//   sees p_j rather than v_j, which flexible GMRES allows (z_j is any vector;
+//   the Arnoldi relation D Z = V H is kept exactly).
 // Per-slot data (masses, basis indices, masks, offsets) live in device
 // memory, so the launch sequence of a step has fixed arguments and is
 // captured once per CGS bucket as a hipGraph and replayed.  Reductions are
@@ -46,7 +59,9 @@ namespace dd {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int KMAX = ENGINE_MAXM + 3;  // reduction slots per rhs
+// Reduction slots per rhs.  The lagged dot pass stores <V_i, w> in slot 2i
+// and <V_i, p> in slot 2i+1; the single-target passes use slots 0..nv-1.
+constexpr int KMAX = 2 * (ENGINE_MAXM + 1) + 2;
 constexpr int K_NORM = KMAX - 2;       // |w|^2
 constexpr int K_MAX = KMAX - 1;        // max|w|
 typedef cx<double> C64;
@@ -85,42 +100,8 @@ __device__ __forceinline__ double wg_max(double v, double *red)
 
 __device__ __forceinline__ int slot_nv(const int *nv_dev, int nvmax, int r) { return nv_dev ? nv_dev[r] : nvmax; }
 
-// Pass 1: partial[g][r][i] = this workgroup's share of <V_i, w>, i < nv_r.
-template <int NV>
-__global__ __launch_bounds__(TPB) void k_dots(const double2 *__restrict__ V, long vstride, int nvmax,
-                                              const int *__restrict__ nv_dev, const double2 *__restrict__ w,
-                                              double2 *__restrict__ partial, int nblocks, int nrhs)
-{
-    __shared__ double red[4];
-    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
-    const int nv = slot_nv(nv_dev, nvmax, r);
-    C64 acc[NV > 0 ? NV : 1];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = mk(0.0, 0.0);
-    for (int b = g; b < nblocks; b += G) {
-        const long base = ((long)b * nrhs + r) * 12 * BS + s;
-        for (int c = 0; c < 12; ++c) {
-            C64 wc = ldc<double>(w + base + c * BS);
-            // unconditional loads keep all NV in flight; slots i >= nv
-            // re-read a valid vector and are never used
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const int ii = i < nv ? i : (nv > 0 ? nv - 1 : 0);
-                cmacc(acc[i], ldc_stream<double>(V + ii * vstride + base + c * BS), wc);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        if (i < nv) { // uniform over the workgroup
-            double re = wg_sum(acc[i].re, red);
-            double im = wg_sum(acc[i].im, red);
-            if (s == 0) partial[((long)g * nrhs + r) * KMAX + i] = make_double2(re, im);
-        }
-    }
-}
-
-// Pass 2: w' = w - sum_{i<nv_r} h[r][i] V_i ; partial <V_i, w'>, |w'|^2, max|w'|.
+// Restart pass: w' = w - sum_{i<nv_r} h[r][i] V_i ; partial <V_i, w'>, |w'|^2,
+// max|w'| (with nv = 0: |w|^2 and max|w| of the restart residual and of b).
 template <int NV>
 __global__ __launch_bounds__(TPB) void k_update_dots(const double2 *__restrict__ V, long vstride, int nvmax,
                                                      const int *__restrict__ nv_dev, const double2 *__restrict__ h,
@@ -191,7 +172,8 @@ __device__ __forceinline__ NormInfo norm_info(const double2 *res, int nv, int r,
     return ni;
 }
 
-// Pass 3: w'' = w' - sum_{i<nv_r} h2[r][i] V_i ; V[dst_r] = w''/h ; lp = scale * V[dst_r].
+// Restart normalisation: w'' = w' - sum_{i<nv_r} h2[r][i] V_i ; V[dst_r] = w''/h ;
+// lp = scale * V[dst_r].
 // Slots with active[r] == 0 write nothing.
 template <int NV, typename SL>
 __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restrict__ V, long vstride, int nvmax,
@@ -229,13 +211,176 @@ __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restr
     }
 }
 
-// Second stage of every reduction: out[r][k] = sum_g partial[g][r][k]
-// (slot K_MAX takes the maximum); fixed order.
-__global__ __launch_bounds__(TPB) void k_reduce(const double2 *__restrict__ partial, double2 *__restrict__ out, int G,
-                                                int nrhs)
+// Lagged pass (A) of step j = nv_r - 1: for i < j the partial sums of
+// <V_i, w> (slot 2i) and <V_i, p> (slot 2i+1) with p = V[j]; <p, w> in slot
+// 2j, |p|^2 in slot 2j+1, |w|^2 in K_NORM.  Inactive slots write nothing.
+template <int NV>
+__global__ __launch_bounds__(TPB) void k_dots_lag(const double2 *__restrict__ V, long vstride,
+                                                  const int *__restrict__ nv_dev, const double2 *__restrict__ w,
+                                                  double2 *__restrict__ partial, const int *__restrict__ active,
+                                                  int nblocks, int nrhs)
 {
     __shared__ double red[4];
-    const int r = blockIdx.y, k = blockIdx.x, s = threadIdx.x;
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const int j = nv_dev[r] - 1;
+    C64 sw[NV > 0 ? NV : 1], sp[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sw[i] = sp[i] = mk(0.0, 0.0);
+    C64 pw = mk(0.0, 0.0);
+    double pp = 0.0, ww = 0.0;
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            const C64 wc = ldc<double>(w + base + c * BS);
+            const C64 pc = ldc_stream<double>(V + j * vstride + base + c * BS);
+            // unconditional loads keep every vector in flight; i >= j re-reads
+            // a valid vector whose sums are never stored
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < j ? i : (j > 0 ? j - 1 : 0);
+                const C64 v = ldc_stream<double>(V + ii * vstride + base + c * BS);
+                cmacc(sw[i], v, wc);
+                cmacc(sp[i], v, pc);
+            }
+            cmacc(pw, pc, wc);
+            pp = fma(pc.re, pc.re, fma(pc.im, pc.im, pp));
+            ww = fma(wc.re, wc.re, fma(wc.im, wc.im, ww));
+        }
+    }
+    double2 *out = partial + ((long)g * nrhs + r) * KMAX;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < j) { // uniform over the workgroup
+            const double a = wg_sum(sw[i].re, red), b = wg_sum(sw[i].im, red);
+            const double c = wg_sum(sp[i].re, red), d = wg_sum(sp[i].im, red);
+            if (s == 0) {
+                out[2 * i] = make_double2(a, b);
+                out[2 * i + 1] = make_double2(c, d);
+            }
+        }
+    }
+    const double a = wg_sum(pw.re, red), b = wg_sum(pw.im, red);
+    const double tp = wg_sum(pp, red), tw = wg_sum(ww, red);
+    if (s == 0) {
+        out[2 * j] = make_double2(a, b);
+        out[2 * j + 1] = make_double2(tp, 0.0);
+        out[K_NORM] = make_double2(tw, 0.0);
+    }
+}
+
+// Coefficients of the lagged update of slot r at step j from the reduced
+// pass-A sums (the same arithmetic runs on the host for the Hessenberg matrix).
+struct LagCoef {
+    double inv_alpha; // 1/alpha (0 when p_j lies in span V[0..j-1])
+    double inv_beta;  // 1/beta (0 on breakdown)
+    C64 hjj;          // <v_j, w>
+};
+__device__ __forceinline__ LagCoef lag_coef(const double2 *row, int j)
+{
+    LagCoef L{1.0, 0.0, mk(row[2 * j].x, row[2 * j].y)};
+    double w2 = row[K_NORM].x;
+    if (j > 0) {
+        double a2 = row[2 * j + 1].x;
+        C64 cs = mk(0.0, 0.0); // c^+ s
+        for (int i = 0; i < j; ++i) {
+            const C64 c = mk(row[2 * i + 1].x, row[2 * i + 1].y), sv = mk(row[2 * i].x, row[2 * i].y);
+            a2 -= c.re * c.re + c.im * c.im;
+            cmacc(cs, c, sv);
+            w2 -= sv.re * sv.re + sv.im * sv.im;
+        }
+        const double al = sqrt(fmax(a2, 0.0));
+        L.inv_alpha = al > 0.0 ? 1.0 / al : 0.0;
+        L.hjj = L.inv_alpha * (L.hjj - cs);
+    }
+    w2 -= L.hjj.re * L.hjj.re + L.hjj.im * L.hjj.im;
+    const double be = sqrt(fmax(w2, 0.0));
+    L.inv_beta = be > 0.0 ? 1.0 / be : 0.0;
+    return L;
+}
+
+// Lagged pass (B) of step j: V[j] = v_j = (p_j - sum_{i<j} c_i V_i)/alpha
+// (j > 0), V[j+1] = p_{j+1} = (w - sum_{i<j} s_i V_i - h_jj v_j)/beta, and
+// lp = p_{j+1} in the smoother precision SL (lp == nullptr: none).  With
+// want_max, max|p_{j+1}| goes to partial slot K_MAX.  Inactive slots write
+// nothing.
+template <int NV, typename SL>
+__global__ __launch_bounds__(TPB) void k_update_lag(double2 *__restrict__ V, long vstride,
+                                                    const int *__restrict__ nv_dev, const double2 *__restrict__ res,
+                                                    const double2 *__restrict__ w, vec2_t<SL> *__restrict__ lp,
+                                                    double2 *__restrict__ partial, int want_max,
+                                                    const int *__restrict__ active, int nblocks, int nrhs)
+{
+    __shared__ double red[4];
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const int j = nv_dev[r] - 1;
+    const double2 *row = res + (long)r * KMAX;
+    const LagCoef L = lag_coef(row, j);
+    C64 cf[NV > 0 ? NV : 1], sf[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        cf[i] = i < j ? ldc<double>(row + 2 * i + 1) : mk(0.0, 0.0);
+        sf[i] = i < j ? ldc<double>(row + 2 * i) : mk(0.0, 0.0);
+    }
+    double2 *vj = V + j * vstride;
+    double2 *pn = V + (j + 1) * vstride;
+    double mx = 0.0;
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) {
+            C64 wc = ldc<double>(w + base + c * BS);
+            C64 pc = ldc_stream<double>(vj + base + c * BS);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int ii = i < j ? i : (j > 0 ? j - 1 : 0); // cf[i] = sf[i] = 0 beyond j
+                const C64 v = ldc_stream<double>(V + ii * vstride + base + c * BS);
+                pc = pc - cf[i] * v;
+                wc = wc - sf[i] * v;
+            }
+            const C64 v = L.inv_alpha * pc;
+            if (j > 0) stc_stream(vj + base + c * BS, v);
+            wc = wc - L.hjj * v;
+            const C64 q = L.inv_beta * wc;
+            stc_stream(pn + base + c * BS, q);
+            if (lp) stc(lp + base + c * BS, q);
+            mx = fmax(mx, fmax(fabs(q.re), fabs(q.im)));
+        }
+    }
+    if (want_max) {
+        const double tm = wg_max(mx, red);
+        if (s == 0) partial[((long)g * nrhs + r) * KMAX + K_MAX] = make_double2(tm, 0.0);
+    }
+}
+
+// FP16 copy of the new basis vector: lp = scale_r * V[nv_r], scale_r =
+// 1/(1.0625 max|V[nv_r]|) (1 for a zero vector), stored in scl[r].
+__global__ __launch_bounds__(TPB) void k_to_half(const double2 *__restrict__ V, long vstride,
+                                                 const int *__restrict__ nv_dev, const double2 *__restrict__ mxred,
+                                                 __half2 *__restrict__ lp, double *__restrict__ scl,
+                                                 const int *__restrict__ active, int nblocks, int nrhs)
+{
+    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
+    if (!active[r]) return;
+    const double m = mxred[(long)r * KMAX + K_MAX].x * 1.0625;
+    const double sc = m > 0.0 ? 1.0 / m : 1.0;
+    if (g == 0 && s == 0) scl[r] = sc;
+    const double2 *src = V + nv_dev[r] * vstride;
+    for (int b = g; b < nblocks; b += G) {
+        const long base = ((long)b * nrhs + r) * 12 * BS + s;
+        for (int c = 0; c < 12; ++c) stc(lp + base + c * BS, sc * ldc_stream<double>(src + base + c * BS));
+    }
+}
+
+// Second stage of every reduction: out[r][k] = sum_g partial[g][r][k]
+// (slot K_MAX takes the maximum); fixed order.
+// The grid covers slots 0..nlead-1 and then K_NORM, K_MAX.
+__global__ __launch_bounds__(TPB) void k_reduce(const double2 *__restrict__ partial, double2 *__restrict__ out, int G,
+                                                int nrhs, int nlead)
+{
+    __shared__ double red[4];
+    const int r = blockIdx.y, s = threadIdx.x;
+    const int k = (int)blockIdx.x < nlead ? (int)blockIdx.x : K_NORM + ((int)blockIdx.x - nlead);
     const bool is_max = (k == K_MAX);
     double re = 0.0, im = 0.0;
     for (int g = s; g < G; g += TPB) {
@@ -366,7 +511,7 @@ struct Engine::Impl {
     DevBuf V, Z, w, xb, bb, lp, sapout, partial, res, res2, resb, y, scl, slots;
     SlotArrays *h_slots[3] = {nullptr, nullptr, nullptr}; // ring of pinned staging buffers
     int ring = 0;
-    double2 *h_res = nullptr, *h_res2 = nullptr, *h_resb = nullptr, *h_y = nullptr;
+    double2 *h_res = nullptr, *h_resb = nullptr, *h_y = nullptr;
     hipEvent_t ev = nullptr;
     std::vector<SlotState> S;
     std::map<int, hipGraphExec_t> graphs;
@@ -378,7 +523,6 @@ struct Engine::Impl {
         for (auto p : h_slots)
             if (p) (void)hipHostFree(p);
         if (h_res) (void)hipHostFree(h_res);
-        if (h_res2) (void)hipHostFree(h_res2);
         if (h_resb) (void)hipHostFree(h_resb);
         if (h_y) (void)hipHostFree(h_y);
         if (ev) (void)hipEventDestroy(ev);
@@ -416,21 +560,48 @@ struct Engine::Impl {
     }
 
     // ---- launch helpers -------------------------------------------------
-    Status dots(const double2 *w, int nvmax)
+    // lagged pass A over V[0..j] and w (nb >= every active slot's j)
+    Status dots_lag(const double2 *wv, int nb)
     {
-        ProfScope ps(ctx->prof, st(), K_CGS_DOTS, vec64() * (nvmax + 1), 8.0 * vlen * nvmax);
-        switch (pick_bucket(nvmax)) {
-#define C(N) case N: k_dots<N><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, N, d_nv(), w, partial.as<double2>(), ctx->g.nblocks, W); break;
+        ProfScope ps(ctx->prof, st(), K_CGS_DOTS, vec64() * (nb + 2), 16.0 * vlen * (nb + 1));
+        switch (pick_bucket(nb)) {
+#define C(N) case N: k_dots_lag<N><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), wv, partial.as<double2>(), d_active(), ctx->g.nblocks, W); break;
             DD_BUCKETS(C)
 #undef C
         }
         DD_HIP_TRY(hipGetLastError());
         return Status::ok();
     }
+    // lagged pass B: v_j over p_j, p_{j+1}, smoother-precision copy
+    template <typename SL> Status update_lag_t(int nb, void *lpp, bool want_max)
+    {
+        ProfScope ps(ctx->prof, st(), K_CGS_UPDATE,
+                     vec64() * (nb + 4) + (lpp ? (double)vlen * 2 * sizeof(SL) : 0.0), 16.0 * vlen * (nb + 1));
+        switch (pick_bucket(nb)) {
+#define C(N) case N: k_update_lag<N, SL><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), res.as<double2>(), w.as<double2>(), static_cast<vec2_t<SL> *>(lpp), partial.as<double2>(), want_max ? 1 : 0, d_active(), ctx->g.nblocks, W); break;
+            DD_BUCKETS(C)
+#undef C
+        }
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
+    Status update_lag(int nb)
+    {
+        if (sap_prec == DD_F64) return update_lag_t<double>(nb, nullptr, false);
+        if (sap_prec == DD_F32) return update_lag_t<float>(nb, lp.p, false);
+        // FP16: the scale needs max|p_{j+1}| first
+        DD_TRY(update_lag_t<float>(nb, nullptr, true));
+        DD_TRY(reduce(res2.as<double2>(), 0));
+        ProfScope ps(ctx->prof, st(), K_CONVERT, vec64() + (double)vlen * 4.0, 2.0 * vlen);
+        k_to_half<<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), res2.as<double2>(), lp.as<__half2>(),
+                                            scl.as<double>(), d_active(), ctx->g.nblocks, W);
+        DD_HIP_TRY(hipGetLastError());
+        return Status::ok();
+    }
     // nvmax == 0: plain |w|^2 and max|w| (no vectors, w untouched)
     Status update_dots(double2 *wv, int nvmax, const double2 *h)
     {
-        ProfScope ps(ctx->prof, st(), K_CGS_UPDATE, vec64() * (nvmax + (nvmax > 0 ? 2 : 1)),
+        ProfScope ps(ctx->prof, st(), K_CGS_NORMALIZE, vec64() * (nvmax + (nvmax > 0 ? 2 : 1)),
                      16.0 * vlen * nvmax + 4.0 * vlen);
         const int *nvp = nvmax > 0 ? d_nv() : nullptr;
         switch (pick_bucket(nvmax)) {
@@ -460,10 +631,11 @@ struct Engine::Impl {
         if (sap_prec == DD_F32) return normalize_t<float>(nvmax, r2, wv, lp.p, false);
         return normalize_t<__half>(nvmax, r2, wv, lp.p, true);
     }
-    Status reduce(double2 *out)
+    // slots 0..nlead-1, K_NORM and K_MAX
+    Status reduce(double2 *out, int nlead)
     {
-        ProfScope ps(ctx->prof, st(), K_REDUCE, (double)G * W * KMAX * 16.0, 0.0);
-        k_reduce<<<dim3(KMAX, W), TPB, 0, st()>>>(partial.as<double2>(), out, G, W);
+        ProfScope ps(ctx->prof, st(), K_REDUCE, (double)G * W * (nlead + 2) * 16.0, 0.0);
+        k_reduce<<<dim3(nlead + 2, W), TPB, 0, st()>>>(partial.as<double2>(), out, G, W, nlead);
         DD_HIP_TRY(hipGetLastError());
         return Status::ok();
     }
@@ -489,8 +661,9 @@ struct Engine::Impl {
         return Status::ok();
     }
 
-    // The fixed launch sequence of one Arnoldi step (captured into a graph).
-    Status step_sequence(int nvmax)
+    // The fixed launch sequence of one Arnoldi step (captured into a graph);
+    // nb >= the Arnoldi index j of every active slot.
+    Status step_sequence(int nb)
     {
         SapSlots ss;
         ss.m0_dev = d_m0();
@@ -520,14 +693,44 @@ struct Engine::Impl {
             DD_HIP_TRY(hipGetLastError());
         }
         DD_TRY(launch_dslash(ctx, nullptr, W, Z.p, zprec, w.p, DD_F64, DD_F64, nullptr, d_m0(), d_in_off(), d_active()));
-        DD_TRY(dots(w.as<double2>(), nvmax));
-        DD_TRY(reduce(res.as<double2>()));
-        DD_TRY(update_dots(w.as<double2>(), nvmax, res.as<double2>()));
-        DD_TRY(reduce(res2.as<double2>()));
-        DD_TRY(normalize(nvmax, res2.as<double2>(), w.as<double2>()));
+        DD_TRY(dots_lag(w.as<double2>(), nb));
+        DD_TRY(reduce(res.as<double2>(), std::min(2 * nb + 2, K_NORM)));
+        DD_TRY(update_lag(nb));
         return Status::ok();
     }
 };
+
+double SlotState::qr(int m, int n)
+{
+    // R = Q^+ H over the leading (n+1) x n block of the unrotated H; g = Q^+ beta0 e_1
+    R = H;
+    std::fill(g.begin(), g.end(), Z64(0.0));
+    g[0] = beta0;
+    for (int k = 0; k < n; ++k) {
+        for (int i = 0; i < k; ++i) {
+            Z64 a = R[(size_t)i * m + k], c = R[(size_t)(i + 1) * m + k];
+            R[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
+            R[(size_t)(i + 1) * m + k] = -std::conj(sn[i]) * a + cs[i] * c;
+        }
+        Z64 rr;
+        givens(R[(size_t)k * m + k], R[(size_t)(k + 1) * m + k], cs[k], sn[k], rr);
+        R[(size_t)k * m + k] = rr;
+        R[(size_t)(k + 1) * m + k] = 0.0;
+        g[k + 1] = -std::conj(sn[k]) * g[k];
+        g[k] = cs[k] * g[k];
+    }
+    return std::abs(g[n]);
+}
+
+void SlotState::solve_y(int m, int n, std::complex<double> *y) const
+{
+    for (int i = 0; i < ENGINE_MAXM; ++i) y[i] = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+        Z64 acc = g[i];
+        for (int k = i + 1; k < n; ++k) acc -= R[(size_t)i * m + k] * y[k];
+        y[i] = acc / R[(size_t)i * m + i];
+    }
+}
 
 Engine::Engine() : d(new Impl()) {}
 Engine::~Engine()
@@ -581,13 +784,13 @@ Status Engine::init(dd_ctx *ctx, const EngineParams &p)
         std::memset(hs, 0, sizeof(SlotArrays));
     }
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_res, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
-    DD_HIP_TRY(hipHostMalloc((void **)&e.h_res2, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_resb, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_y, (size_t)e.W * ENGINE_MAXM * 16, hipHostMallocDefault));
     DD_HIP_TRY(hipEventCreateWithFlags(&e.ev, hipEventDisableTiming));
     e.S.assign(e.W, SlotState{});
     for (auto &s : e.S) {
         s.H.assign((size_t)(p.m + 1) * p.m, 0.0);
+        s.R.assign((size_t)(p.m + 1) * p.m, 0.0);
         s.g.assign(p.m + 1, 0.0);
         s.sn.assign(p.m, 0.0);
         s.cs.assign(p.m, 0.0);
@@ -673,14 +876,14 @@ Status Engine::launch_restart()
     if (bn) {
         // |b| of newly admitted slots
         DD_TRY(e.update_dots(e.bb.as<double2>(), 0, nullptr));
-        DD_TRY(e.reduce(e.resb.as<double2>()));
+        DD_TRY(e.reduce(e.resb.as<double2>(), 0));
         DD_HIP_TRY(hipMemcpyAsync(e.h_resb, e.resb.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
         e.bnorm_pending = true;
     }
     // true residual r = b - D x (FP64) for every slot; |r|, max|r|; v_0 for restarting slots
     DD_TRY(launch_dslash(e.ctx, nullptr, e.W, e.xb.p, DD_F64, e.w.p, DD_F64, DD_F64, e.bb.as<double>(), e.d_m0()));
     DD_TRY(e.update_dots(e.w.as<double2>(), 0, nullptr));
-    DD_TRY(e.reduce(e.res.as<double2>()));
+    DD_TRY(e.reduce(e.res.as<double2>(), 0));
     DD_TRY(e.normalize(0, e.res.as<double2>(), e.w.as<double2>()));
     DD_HIP_TRY(hipMemcpyAsync(e.h_res, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
     DD_HIP_TRY(hipEventRecord(e.ev, e.st()));
@@ -727,8 +930,8 @@ Status Engine::finish_restart()
             continue;
         }
         s.info.restarts++;
-        std::fill(s.g.begin(), s.g.end(), Z64(0.0));
-        s.g[0] = beta;
+        s.beta0 = beta;
+        s.beta_prev = 0.0;
         s.j = 0;
         s.state = SLOT_CYCLE;
     }
@@ -740,10 +943,10 @@ Status Engine::launch_step()
 {
     Impl &e = *d;
     e.step_pending = false;
-    int nvmax = 0;
+    int jmax = -1;
     for (auto &s : e.S)
-        if (s.state == SLOT_CYCLE) nvmax = std::max(nvmax, s.j + 1);
-    if (nvmax == 0) return Status::ok();
+        if (s.state == SLOT_CYCLE) jmax = std::max(jmax, s.j);
+    if (jmax < 0) return Status::ok();
     SlotArrays &h = e.stage();
     e.fill_common(h);
     for (int r = 0; r < ENGINE_MAXW; ++r) {
@@ -757,7 +960,7 @@ Status Engine::launch_step()
         h.in_off[r] = (long)j * e.vlen;
     }
     DD_TRY(e.upload(h));
-    const int bucket = pick_bucket(nvmax);
+    const int bucket = pick_bucket(jmax);
     const bool use_graph = e.P.graphs && !e.ctx->prof.on;
     if (use_graph) {
         const int key = bucket * 4 + e.sap_prec;
@@ -783,7 +986,6 @@ Status Engine::launch_step()
         DD_TRY(e.step_sequence(bucket));
     }
     DD_HIP_TRY(hipMemcpyAsync(e.h_res, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
-    DD_HIP_TRY(hipMemcpyAsync(e.h_res2, e.res2.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
     DD_HIP_TRY(hipEventRecord(e.ev, e.st()));
     e.step_pending = true;
     return Status::ok();
@@ -802,48 +1004,62 @@ Status Engine::finish_step()
         SlotState &s = e.S[r];
         Z64 *yr = reinterpret_cast<Z64 *>(e.h_y + (size_t)r * ENGINE_MAXM);
         if (s.state != SLOT_CYCLE) continue;
-        const int j = s.j, nv = j + 1;
-        const double2 *h1 = e.h_res + (size_t)r * KMAX;
-        const double2 *h2 = e.h_res2 + (size_t)r * KMAX;
-        double hh = h2[K_NORM].x;
-        for (int i = 0; i < nv; ++i) {
-            s.H[(size_t)i * m + j] = Z64(h1[i].x, h1[i].y) + Z64(h2[i].x, h2[i].y);
-            hh -= h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+        const int j = s.j;
+        const double2 *row = e.h_res + (size_t)r * KMAX;
+        auto sv = [&](int i) { return Z64(row[2 * i].x, row[2 * i].y); };
+        auto cv = [&](int i) { return Z64(row[2 * i + 1].x, row[2 * i + 1].y); };
+        // finish column j-1: p_j = V c + alpha v_j
+        double alpha = 1.0, w2 = row[K_NORM].x;
+        Z64 hjj = sv(j);
+        bool ok_prev = true;
+        if (j > 0) {
+            double a2 = row[2 * j + 1].x;
+            Z64 cs(0.0);
+            for (int i = 0; i < j; ++i) {
+                a2 -= std::norm(cv(i));
+                cs += std::conj(cv(i)) * sv(i);
+                w2 -= std::norm(sv(i));
+            }
+            ok_prev = std::isfinite(a2);
+            alpha = std::sqrt(std::max(a2, 0.0));
+            if (ok_prev) {
+                for (int i = 0; i < j; ++i) s.H[(size_t)i * m + j - 1] += s.beta_prev * cv(i);
+                s.H[(size_t)j * m + j - 1] = s.beta_prev * alpha;
+            }
+            hjj = alpha > 0.0 ? (hjj - cs) / alpha : Z64(0.0);
         }
-        const double hn = std::sqrt(std::max(hh, 0.0));
-        s.H[(size_t)(j + 1) * m + j] = hn;
-        for (int i = 0; i < j; ++i) {
-            Z64 a = s.H[(size_t)i * m + j], c = s.H[(size_t)(i + 1) * m + j];
-            s.H[(size_t)i * m + j] = s.cs[i] * a + s.sn[i] * c;
-            s.H[(size_t)(i + 1) * m + j] = -std::conj(s.sn[i]) * a + s.cs[i] * c;
-        }
-        Z64 rr;
-        givens(s.H[(size_t)j * m + j], s.H[(size_t)(j + 1) * m + j], s.cs[j], s.sn[j], rr);
-        s.H[(size_t)j * m + j] = rr;
-        s.H[(size_t)(j + 1) * m + j] = 0.0;
-        s.g[j + 1] = -std::conj(s.sn[j]) * s.g[j];
-        s.g[j] = s.cs[j] * s.g[j];
+        // column j as it stands
+        for (int i = 0; i < j; ++i) s.H[(size_t)i * m + j] = sv(i);
+        s.H[(size_t)j * m + j] = hjj;
+        w2 -= std::norm(hjj);
+        const bool ok_cur = std::isfinite(w2);
+        const double beta = std::sqrt(std::max(w2, 0.0));
+        s.H[(size_t)(j + 1) * m + j] = beta;
+        s.beta_prev = beta;
         s.info.iterations++;
         s.info.sap_calls++;
-        s.j = j + 1;
-        const bool finite = std::isfinite(hn) && std::isfinite(std::abs(rr));
-        if (!finite) {
-            s.j = j; // drop the broken column; the restart recomputes the true residual
-            broken = true;
+        int ncols = j + 1;
+        bool end = false;
+        if (!ok_prev) { // cannot happen with finite data; drop both columns
+            ncols = j - 1;
+            broken = end = true;
+        } else if (j > 0 && alpha == 0.0) { // p_j in span V: column j-1 ended the space
+            ncols = j;
+            end = true;
+        } else if (!ok_cur) { // drop the broken column; the restart recomputes the true residual
+            ncols = j;
+            broken = end = true;
         }
-        if (!finite || hn == 0.0 || std::abs(s.g[j + 1]) / s.bnorm <= e.P.tol || s.j == m) {
+        const double est = s.qr(m, ncols);
+        if (beta == 0.0 || !(est / s.bnorm > e.P.tol) || ncols == m) end = true;
+        s.j = ncols;
+        if (end) {
             // end of this slot's cycle: y = R^-1 g, then x += Z y
-            const int len = s.j;
-            for (int i = 0; i < ENGINE_MAXM; ++i) yr[i] = 0.0;
-            for (int i = len - 1; i >= 0; --i) {
-                Z64 acc = s.g[i];
-                for (int k = i + 1; k < len; ++k) acc -= s.H[(size_t)i * m + k] * yr[k];
-                yr[i] = acc / s.H[(size_t)i * m + i];
-            }
+            s.solve_y(m, ncols, yr);
             s.state = SLOT_RESTART;
-            s.cycle_len = len;
+            s.cycle_len = ncols;
             any_end = true;
-            maxlen = std::max(maxlen, len);
+            maxlen = std::max(maxlen, ncols);
         }
     }
     if (broken && e.sap_prec == DD_F16) {
@@ -854,12 +1070,8 @@ Status Engine::finish_step()
             if (s.state != SLOT_CYCLE) continue;
             Z64 *yr = reinterpret_cast<Z64 *>(e.h_y + (size_t)r * ENGINE_MAXM);
             const int len = s.j;
-            for (int i = 0; i < ENGINE_MAXM; ++i) yr[i] = 0.0;
-            for (int i = len - 1; i >= 0; --i) {
-                Z64 acc = s.g[i];
-                for (int k = i + 1; k < len; ++k) acc -= s.H[(size_t)i * m + k] * yr[k];
-                yr[i] = acc / s.H[(size_t)i * m + i];
-            }
+            (void)s.qr(m, len);
+            s.solve_y(m, len, yr);
             s.state = SLOT_RESTART;
             s.cycle_len = len;
             any_end = true;

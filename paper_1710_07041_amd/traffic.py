@@ -31,9 +31,10 @@ CLASS_PATTERNS = [
     (r"k_dslash<double, double,", "dslash_f64"),
     (r"k_dslash<float, float,", "dslash_f32"),
     (r"k_dslash<__half,", "dslash_f16"),
-    (r"k_dots<", "cgs_dots"),
-    (r"k_update_dots<", "cgs_update_dots"),
-    (r"k_update_normalize<", "cgs_update_normalize"),
+    (r"k_dots_lag<", "cgs_dots"),
+    (r"k_update_lag<", "cgs_update"),
+    (r"k_update_dots<", "restart_norm"),
+    (r"k_update_normalize<", "restart_norm"),
 ]
 
 
