@@ -268,6 +268,90 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
     }
 }
 
+// ---------------------------------------------------------------------------
+// Face buffers of the Schwarz sweep.  A block that has just been solved
+// publishes, for each of its boundary sites, the half spinor that the
+// neighbouring block (of the other colour) needs for the hop into it:
+//   face 2 mu     (sites with l_mu = 0): h = (1 - gamma_mu) psi, projected,
+//                 for the +mu hop of the block below, which applies its own
+//                 link U_mu(x);
+//   face 2 mu + 1 (sites with l_mu = 3): t = U~_mu(y)^+ (1 + gamma_mu) psi,
+//                 projected, with U~ = -U/2 the register-resident link, for
+//                 the -mu hop of the block above.
+// The consumer then reads six components per boundary hop, dense in a row of
+// 64 face sites, instead of the neighbour's twelve (strided) and its link.
+// Layout per block and right-hand side: [face 0..7][half-spinor comp. 0..5][64].
+constexpr int FACE_ELEMS = 8 * 6 * 64; // = 12 * BS: one spinor's worth per block
+
+// Position of site s in the face of direction mu (the other three
+// coordinates, 2 bits each, in order).
+__device__ __forceinline__ int face_index(int s, int mu)
+{
+    const int lo = s & ((1 << (2 * mu)) - 1);
+    return lo | ((s >> (2 * mu + 2)) << (2 * mu));
+}
+
+template <typename S, typename A>
+__device__ __forceinline__ void face_publish(vec2_t<S> *__restrict__ F, int b, int nrhs, int r, int s,
+                                             const cx<A> p[12], const cx<A> Ur[4][9])
+{
+    vec2_t<S> *base = F + ((long)b * nrhs + r) * FACE_ELEMS;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int l = (s >> (2 * mu)) & 3;
+        cx<A> h[6], t[6];
+        if (l == 0) {
+            proj_m(mu, p, h);
+            vec2_t<S> *fp = base + (2 * mu) * 6 * 64 + face_index(s, mu);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) stc(fp + e * 64, h[e]);
+        } else if (l == BEXT - 1) {
+            proj_p(mu, p, h);
+            su3_mul_adj(Ur[mu], h, t);
+            vec2_t<S> *fp = base + (2 * mu + 1) * 6 * 64 + face_index(s, mu);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) stc(fp + e * 64, t[e]);
+        }
+    }
+}
+
+// The boundary hops of site s from the faces the neighbouring blocks
+// published, accumulated into q (one direction per trip: the register
+// budget of the sweep has no room for more face data in flight).
+template <typename S, typename A>
+__device__ __forceinline__ void face_consume(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
+                                             const vec2_t<S> *__restrict__ F, const cx<A> Ur[4][9], cx<A> q[12])
+{
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        const int l = (s >> (2 * mu)) & 3;
+        if (l != 0 && l != BEXT - 1) continue;
+        const int dir = l == 0 ? -1 : 1;
+        int bn, sn, sign;
+        bool inb;
+        neighbour_rt(g, b, bc, s, mu, dir, bn, sn, sign, inb);
+        if (inb) continue;
+        // the +mu face of the block below, or the -mu face of the block above
+        const vec2_t<S> *fp =
+            F + ((long)bn * nrhs + r) * FACE_ELEMS + (2 * mu + (dir < 0 ? 1 : 0)) * 6 * 64 + face_index(s, mu);
+        cx<A> h[6], t[6], U[9];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) h[e] = ldc<A>(fp + e * 64);
+        // U~ and the published t carry -1/2: only the boundary sign remains
+        if (dir > 0) {
+            // explicit branches: a switch would become a dynamic register index
+            if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }
+            else if (mu == 1) { for (int e = 0; e < 9; ++e) U[e] = Ur[1][e]; }
+            else if (mu == 2) { for (int e = 0; e < 9; ++e) U[e] = Ur[2][e]; }
+            else { for (int e = 0; e < 9; ++e) U[e] = Ur[3][e]; }
+            su3_mul(U, h, t);
+            recon_m(mu, q, t, (A)sign);
+        } else {
+            recon_p(mu, q, h, (A)sign);
+        }
+    }
+}
+
 template <typename A> __device__ __forceinline__ A wave_sum(A v)
 {
 #pragma unroll

@@ -50,6 +50,7 @@ struct SArgs {
     const long *eta_off;  // per-rhs element offsets of eta and psi (nullable)
     const long *psi_off;
     const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
+    int publish;          // write the face buffers for the next sweep
 };
 
 // The MR coefficient of one right-hand side: the dot products <q, r> and
@@ -96,9 +97,10 @@ template <typename A, typename RES> struct DelStore {
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
     const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
-    const vec2_t<S> *__restrict__ clov, SArgs a)
+    const vec2_t<S> *__restrict__ clov, vec2_t<S> *__restrict__ faces, SArgs a)
 {
     constexpr bool REGLINKS = RES::links;
+    static_assert(REGLINKS, "the face buffers assume register-resident links");
     __shared__ Lds<A> L;
     __shared__ DelStore<A, RES> D;
     const int i = xcd_remap(blockIdx.x, gridDim.x);
@@ -158,7 +160,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
                 for (int c = 0; c < 12; ++c) del[c] = d0[c];
             }
         }
-        if (a.mode != 0) face_hops<S, S, A, REGLINKS>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+        // the boundary hops, from the faces the other colour published
+        if (a.mode != 0) face_consume<S, A>(a.g, b, bc, s, r, a.nrhs, faces, U, q);
         // rho = eta - (D psi)_B
 #pragma unroll
         for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(eta + sp + c * BS) - q[c];
@@ -180,13 +183,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
                 rr[c] = rr[c] - alpha * q[c];
             }
         }
-        if constexpr (RES::clover_half) {
+        cx<A> fin[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, D.d[c][s]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, del[c]);
+        for (int c = 0; c < 12; ++c) {
+            if constexpr (RES::clover_half) fin[c] = D.d[c][s];
+            else fin[c] = del[c];
+            vec2_t<S> v;
+            stc(&v, fin[c]);
+            psi[sp + c * BS] = v;
+            fin[c] = ldc<A>(&v); // the stored value, as the other colour would read it
         }
+        if (a.publish) face_publish<S, A>(faces, b, a.nrhs, r, s, fin, U);
     }
 }
 
@@ -533,7 +540,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 }
 
 template <typename S, typename A, typename RES, bool EO>
-Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
+Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces)
 {
     // algorithmic traffic of one colour sweep: links + clover once, eta, psi
     // (read only when nonzero) and psi written, per swept site and rhs
@@ -554,7 +561,7 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi)
         k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
             static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
-            a);
+            static_cast<vec2_t<S> *>(faces), a);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
@@ -571,6 +578,13 @@ typedef Residency<true, false, 1, true> ResF64;
 typedef Residency<true, false, 1, true> ResEO;
 
 } // namespace
+
+Status reserve_sap_faces(dd_ctx *ctx, int prec, int nrhs)
+{
+    const size_t need = spinor_bytes(ctx->g, prec, nrhs); // FACE_ELEMS = 12 * BS per block and rhs
+    if (ctx->sap_faces.p && ctx->sap_faces.bytes >= need) return Status::ok();
+    return ctx->sap_faces.alloc(need);
+}
 
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
                const SapSlots *slots, bool eo)
@@ -598,20 +612,28 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
         a.psi_off = slots->psi_off;
         a.active = slots->active;
     }
+    // face buffers (plain sweep): the caller's, else the context's
+    void *faces = slots ? slots->faces : nullptr;
+    if (!eo && !faces) {
+        DD_TRY(reserve_sap_faces(ctx, prec, nrhs));
+        faces = ctx->sap_faces.p;
+    }
+    if (!eo && !faces) return Status{DD_INVALID_ARG, "SAP: no face buffer"};
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;
             a.blocks = ctx->colour_blocks[col].as<int>();
             a.nblk = ctx->ncolour[col];
             a.mode = (cy == 0 && col == 0) ? 0 : (cy == 0 ? 1 : 2);
+            a.publish = !(cy == ncy - 1 && col == 1);
             if (eo) {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi)));
-                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi, faces)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi, faces)));
+                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces)));
             } else {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi)));
-                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces)));
+                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces)));
             }
         }
     return Status::ok();
