@@ -160,11 +160,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
                 for (int c = 0; c < 12; ++c) del[c] = d0[c];
             }
         }
+        // eta in flight during the face trips (held in the storage type)
+        vec2_t<S> er[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) er[c] = eta[sp + c * BS];
         // the boundary hops, from the faces the other colour published
         if (a.mode != 0) face_consume<S, A>(a.g, b, bc, s, r, a.nrhs, faces, U, q);
         // rho = eta - (D psi)_B
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(eta + sp + c * BS) - q[c];
+        for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(&er[c]) - q[c];
         // MR on D_BB
         for (int it = 0; it < a.nmr; ++it) {
             block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
