@@ -22,10 +22,12 @@
 // last-level cache in FP32); links and clover half 0, read once per sweep,
 // stream.
 // The block residual eta_B - (D psi)_B is formed on entry: the in-block part
-// by the same LDS exchange, the hops that leave the block by reading the
-// other colour's psi (and, for -mu hops, the neighbour's link) from memory.
-// Blocks of one colour share no site and read only the other colour's psi,
-// so a sweep needs no synchronisation between workgroups.
+// by the same LDS exchange, the hops that leave the block from the face
+// buffers that the other colour's blocks published at the end of their
+// solves (block_ops.h: six dense components per boundary hop instead of the
+// neighbour's twelve and its link).  Blocks of one colour share no site and
+// read only the other colour's data, so a sweep needs no synchronisation
+// between workgroups.
 //
 // k_sap_sweep_eo is the same sweep with the even-odd preconditioned block
 // solve (MR on the even-site Schur complement, odd sites reconstructed);
@@ -216,6 +218,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 // term is small against 4 + m0).
 // ---------------------------------------------------------------------------
 
+// Whether the even-odd sweep of storage type S uses the face buffers.
+template <typename S> constexpr bool EO_FACES = !std::is_same<S, double>::value;
+
 // Site of thread t: the pair {2k, 2k+1} (k = t mod 128) holds one even and
 // one odd site; which is which follows from (ly + lz + lt) mod 2.
 __device__ __forceinline__ int eo_site(int t)
@@ -379,7 +384,7 @@ template <typename A> __device__ __forceinline__ void chol_solve_lds(const cx<A>
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep_eo(
     const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
-    const vec2_t<S> *__restrict__ clov, SArgs a)
+    const vec2_t<S> *__restrict__ clov, vec2_t<S> *__restrict__ faces, SArgs a)
 {
     static_assert(RES::links && RES::clover_half, "even-odd sweep: links and clover half 0 in registers");
     __shared__ SapEoShared<A> SH;
@@ -439,9 +444,22 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
             }
         }
-        if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+        // the boundary hops, from the faces the other colour published, with
+        // eta in flight during the face trips (in FP64 the other colour's psi
+        // and links are read instead, and eta afterwards: the face code does
+        // not fit this sweep's FP64 register budget)
+        if constexpr (EO_FACES<S>) {
+            vec2_t<S> er[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(eta + sp + c * BS) - q[c];
+            for (int c = 0; c < 12; ++c) er[c] = eta[sp + c * BS];
+            if (a.mode != 0) face_consume<S, A>(a.g, b, bc, s, r, a.nrhs, faces, U, q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(&er[c]) - q[c];
+        } else {
+            if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(eta + sp + c * BS) - q[c];
+        }
         // the parity exchanges reuse the memory of the full one
         __syncthreads();
 
@@ -537,7 +555,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
             for (int c = 0; c < 12; ++c) rr[c] = rr[c] + ldc<A>(psi + sp + c * BS);
         }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) stc(psi + sp + c * BS, rr[c]);
+        for (int c = 0; c < 12; ++c) {
+            vec2_t<S> v;
+            stc(&v, rr[c]);
+            psi[sp + c * BS] = v;
+            rr[c] = ldc<A>(&v); // the stored value, as the other colour would read it
+        }
+        if constexpr (EO_FACES<S>) {
+            if (a.publish) face_publish<S, A>(faces, b, a.nrhs, r, s, rr, U);
+        }
         // the next right-hand side's residual reuses the LDS read above
         __syncthreads();
     }
@@ -560,7 +586,7 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
         k_sap_sweep_eo<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
             static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
-            a);
+            static_cast<vec2_t<S> *>(faces), a);
     else
         k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
@@ -616,13 +642,13 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
         a.psi_off = slots->psi_off;
         a.active = slots->active;
     }
-    // face buffers (plain sweep): the caller's, else the context's
+    // face buffers: the caller's, else the context's
     void *faces = slots ? slots->faces : nullptr;
-    if (!eo && !faces) {
+    if (!faces) {
         DD_TRY(reserve_sap_faces(ctx, prec, nrhs));
         faces = ctx->sap_faces.p;
     }
-    if (!eo && !faces) return Status{DD_INVALID_ARG, "SAP: no face buffer"};
+    if (!faces) return Status{DD_INVALID_ARG, "SAP: no face buffer"};
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;
