@@ -211,11 +211,14 @@ __global__ __launch_bounds__(TPB) void k_update_normalize(const double2 *__restr
     }
 }
 
-// Lagged pass (A) of step j = nv_r - 1: for i < j the partial sums of
+// Lagged pass (A) of step j = nv_r - 1 (from 12 to 18 vectors the kernel is
+// pinned to two waves per SIMD: left to itself the compiler picks a
+// three-wave schedule for some of these sizes that keeps fewer loads in
+// flight and runs up to 1.6x slower).  For i < j the partial sums of
 // <V_i, w> (slot 2i) and <V_i, p> (slot 2i+1) with p = V[j]; <p, w> in slot
 // 2j, |p|^2 in slot 2j+1, |w|^2 in K_NORM.  Inactive slots write nothing.
 template <int NV>
-__global__ __launch_bounds__(TPB) void k_dots_lag(const double2 *__restrict__ V, long vstride,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(NV >= 12 && NV < 20 ? 2 : 1, NV >= 12 && NV < 20 ? 2 : 8))) void k_dots_lag(const double2 *__restrict__ V, long vstride,
                                                   const int *__restrict__ nv_dev, const double2 *__restrict__ w,
                                                   double2 *__restrict__ partial, const int *__restrict__ active,
                                                   int nblocks, int nrhs)
