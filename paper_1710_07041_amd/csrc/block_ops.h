@@ -104,15 +104,62 @@ __device__ __forceinline__ void get_link(const cx<A> Ur[4][9], const vec2_t<S> *
     }
 }
 
-// One direction of the LDS exchange with the link given in registers, already
-// multiplied by the hop factor -1/2.  In-block neighbours carry the boundary
-// sign only when the block spans the whole direction (one block per
-// direction); otherwise the reconstruction is a plain sum.
-template <int MU, typename S, typename A>
+// The complex value that lane (src4 / 4) of this wavefront holds in v
+// (ds_bpermute: a cross-lane read, no LDS storage and no barrier).
+template <typename A> __device__ __forceinline__ cx<A> lane_fetch(const cx<A> &v, int src4)
+{
+    if constexpr (sizeof(A) == 4) {
+        return mk<A>(__int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(v.re))),
+                     __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(v.im))));
+    } else {
+        const long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
+        const int r0 = __builtin_amdgcn_ds_bpermute(src4, (int)r), r1 = __builtin_amdgcn_ds_bpermute(src4, (int)(r >> 32));
+        const int i0 = __builtin_amdgcn_ds_bpermute(src4, (int)i), i1 = __builtin_amdgcn_ds_bpermute(src4, (int)(i >> 32));
+        return mk<A>(__longlong_as_double(((long long)r1 << 32) | (unsigned)r0),
+                     __longlong_as_double(((long long)i1 << 32) | (unsigned)i0));
+    }
+}
+
+// One direction of the in-block exchange with the link given in registers,
+// already multiplied by the hop factor -1/2.  With LANES (site s = x + 4y +
+// 16z + 64t of the 4^4 block is thread s) a wavefront holds one t-slice: the
+// x, y and z neighbours are lanes of the same wavefront and are read across
+// lanes; only the t direction goes through LDS and a barrier.  Without LANES
+// (another site-to-thread map) every direction goes through LDS.  In-block
+// neighbours carry the boundary sign only when the block spans the whole
+// direction (one block per direction); otherwise the reconstruction is a
+// plain sum.
+template <int MU, typename S, typename A, bool LANES>
 __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
                                              const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
 {
     const bool wraps = g.nb[MU] == 1; // uniform
+    if constexpr (LANES && MU < 3) {
+        cx<A> h[6], t[6];
+        int bn, snf, snb, sign_f, sign_b;
+        bool inf, inbk;
+        neighbour<MU, +1>(g, b, bc, s, bn, snf, sign_f, inf);
+        neighbour<MU, -1>(g, b, bc, s, bn, snb, sign_b, inbk);
+        // +mu hop: the neighbour's projected half spinor, times this site's link
+        proj_minus<MU>(v, h);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = lane_fetch<A>(h[c], (snf & 63) << 2);
+        if (inf) {
+            su3_mul(U, t, h);
+            if (wraps) recon_minus<MU>(q, h, (A)sign_f);
+            else recon_minus1<MU>(q, h);
+        }
+        // -mu hop: U^+ of the neighbour times its projected half spinor
+        proj_plus<MU>(v, h);
+        su3_mul_adj(U, h, t);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) h[c] = lane_fetch<A>(t[c], (snb & 63) << 2);
+        if (inbk) {
+            if (wraps) recon_plus<MU>(q, h, (A)sign_b);
+            else recon_plus1<MU>(q, h);
+        }
+        return;
+    }
     constexpr int X = MU & 1;
     cx<A> h[6], t[6];
     proj_minus<MU>(v, h);
@@ -142,11 +189,12 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
     }
 }
 
-// q = D_BB v on the block (all threads of the workgroup take part).  The
-// loops over clover halves and directions are kept as loops so that only one
-// step's loads are in flight per thread (unrolled, the compiler hoists them
-// all and spills).
-template <typename S, typename A, typename RES, bool NTC = false>
+// q = D_BB v on the block (all threads of the workgroup take part; LANES:
+// thread s holds site s, which lets the x, y and z hops stay inside a
+// wavefront).  The loops over clover halves and directions are kept as loops
+// so that only one step's loads are in flight per thread (unrolled, the
+// compiler hoists them all and spills).
+template <typename S, typename A, typename RES, bool NTC = false, bool LANES = true>
 __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
                                             const cx<A> Ur[RES::links ? 4 : 1][9], const cx<A> cl[RES::ncl],
                                             const vec2_t<S> *__restrict__ links_g,
@@ -180,10 +228,10 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
     }
     if constexpr (RES::links) {
         // links already in registers: no loads to hoist, unroll the directions
-        exchange_dir<0, S, A>(L, g, b, bc, s, Ur[0], v, q);
-        exchange_dir<1, S, A>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
-        exchange_dir<2, S, A>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
-        exchange_dir<3, S, A>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        exchange_dir<0, S, A, LANES>(L, g, b, bc, s, Ur[0], v, q);
+        exchange_dir<1, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
+        exchange_dir<2, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
+        exchange_dir<3, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
     } else {
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {

@@ -438,7 +438,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
             if (a.mode == 2) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) p0[c] = ldc<A>(psi + sp + c * BS);
-                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, p0, q);
+                // threads own sites by parity here, not site = thread
+                block_apply<S, A, RES, false, false>(L, a.g, b, bc, s, U, cl, links, clov, diag, p0, q);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
