@@ -318,12 +318,13 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
 
 // ---------------------------------------------------------------------------
 // Face buffers of the Schwarz sweep.  A block that has just been solved
-// publishes, for each of its boundary sites, the half spinor that the
-// neighbouring block (of the other colour) needs for the hop into it:
-//   face 2 mu     (sites with l_mu = 0): h = (1 - gamma_mu) psi, projected,
+// publishes, for each of its boundary sites and a spinor p (its update delta
+// in the plain sweep, its psi in the even-odd sweep), the half spinor that
+// the neighbouring block (of the other colour) needs for the hop into it:
+//   face 2 mu     (sites with l_mu = 0): h = (1 - gamma_mu) p, projected,
 //                 for the +mu hop of the block below, which applies its own
 //                 link U_mu(x);
-//   face 2 mu + 1 (sites with l_mu = 3): t = U~_mu(y)^+ (1 + gamma_mu) psi,
+//   face 2 mu + 1 (sites with l_mu = 3): t = U~_mu(y)^+ (1 + gamma_mu) p,
 //                 projected, with U~ = -U/2 the register-resident link, for
 //                 the -mu hop of the block above.
 // The consumer then reads six components per boundary hop, dense in a row of

@@ -127,7 +127,7 @@ struct dd_ctx {
     dd::DevBuf colour_blocks[2]; // int block ids of each colour, XCD-friendly order
     int ncolour[2] = {0, 0};
     std::string err;
-    dd::DevBuf sap_faces; // face buffers of the Schwarz sweeps of dd_sap
+    dd::DevBuf sap_scratch; // face buffers and carried residual of the Schwarz sweeps of dd_sap
     dd::Prof prof;
     std::unique_ptr<dd::Engine, dd::EngineDeleter> engine; // reused by dd_solve
 };
@@ -167,12 +167,13 @@ struct SapSlots {
     const long *eta_off = nullptr;
     const long *psi_off = nullptr;
     const int *active = nullptr; // slots with active[r] == 0 are skipped (psi left as it was)
-    // face buffers of the plain sweep: nrhs spinors of the smoother precision
-    // (spinor_bytes), owned by the caller; must be set with per-slot data
-    void *faces = nullptr;
+    // the sweeps' scratch (face buffers and the carried block residual,
+    // sap_scratch_bytes), owned by the caller; must be set with per-slot data
+    void *scratch = nullptr;
 };
-// grows the context's face buffer (used when no SapSlots::faces is given)
-Status reserve_sap_faces(dd_ctx *ctx, int prec, int nrhs);
+size_t sap_scratch_bytes(const GeomHost &g, int prec, int nrhs);
+// grows the context's scratch (used when no SapSlots::scratch is given)
+Status reserve_sap_scratch(dd_ctx *ctx, int prec, int nrhs);
 // eo selects the even-odd preconditioned block solve
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
                const SapSlots *slots = nullptr, bool eo = false);

@@ -511,7 +511,7 @@ struct Engine::Impl {
     int sap_prec = DD_F32;
     long vlen = 0; // complex entries of one width-wide vector
     int G = 0;
-    DevBuf V, Z, w, xb, bb, lp, sapout, faces, partial, res, res2, resb, y, scl, slots;
+    DevBuf V, Z, w, xb, bb, lp, sapout, sapscr, partial, res, res2, resb, y, scl, slots;
     SlotArrays *h_slots[3] = {nullptr, nullptr, nullptr}; // ring of pinned staging buffers
     int ring = 0;
     double2 *h_res = nullptr, *h_resb = nullptr, *h_y = nullptr;
@@ -671,7 +671,7 @@ struct Engine::Impl {
         SapSlots ss;
         ss.m0_dev = d_m0();
         ss.active = d_active(); // done or empty slots cost no smoother work
-        ss.faces = faces.p;
+        ss.scratch = sapscr.p;
         if (P.ncy == 0) {
             // no smoother: z_j = v_j (the smoother-precision copy, or V itself in FP64)
             ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 2 * 2 * real_bytes(zprec), 0.0);
@@ -748,8 +748,9 @@ size_t Engine::bytes_per_slot(const GeomHost &g, int m, int sap_prec)
     size_t zb = (size_t)g.V * 12 * 2 * real_bytes(sap_prec == DD_F64 ? DD_F64 : DD_F32);
     size_t lpb = sap_prec == DD_F64 ? 0 : (size_t)g.V * 12 * 2 * real_bytes(DD_F32);
     size_t so = sap_prec == DD_F16 ? (size_t)g.V * 12 * 4 : 0;
-    // the smoother's face buffers take one vector of Z's precision
-    return v * (m + 1 + 3) + zb * (m + 1) + lpb + so;
+    // the smoother's scratch (face buffers, carried residual) takes two
+    // vectors of Z's precision
+    return v * (m + 1 + 3) + zb * (m + 2) + lpb + so;
 }
 
 int Engine::width() const { return d->W; }
@@ -777,8 +778,8 @@ Status Engine::init(dd_ctx *ctx, const EngineParams &p)
     DD_TRY(e.bb.alloc(v64));
     if (p.sap_prec != DD_F64) DD_TRY(e.lp.alloc((size_t)e.vlen * 2 * real_bytes(DD_F32))); // room for an FP32 fallback
     if (p.sap_prec == DD_F16) DD_TRY(e.sapout.alloc((size_t)e.vlen * 2 * real_bytes(DD_F16)));
-    // smoother face buffers, sized for FP32 so that an FP16 engine can fall back
-    DD_TRY(e.faces.alloc((size_t)e.vlen * 2 * real_bytes(e.zprec)));
+    // smoother scratch, sized for FP32 so that an FP16 engine can fall back
+    DD_TRY(e.sapscr.alloc(sap_scratch_bytes(ctx->g, e.zprec, e.W)));
     DD_TRY(e.partial.alloc((size_t)e.G * e.W * KMAX * 16));
     DD_TRY(e.res.alloc((size_t)e.W * KMAX * 16));
     DD_TRY(e.res2.alloc((size_t)e.W * KMAX * 16));

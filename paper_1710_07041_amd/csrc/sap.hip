@@ -21,13 +21,17 @@
 // by the operator that follows the smoother, and fit in the 256 MB
 // last-level cache in FP32); links and clover half 0, read once per sweep,
 // stream.
-// The block residual eta_B - (D psi)_B is formed on entry: the in-block part
-// by the same LDS exchange, the hops that leave the block from the face
-// buffers that the other colour's blocks published at the end of their
-// solves (block_ops.h: six dense components per boundary hop instead of the
-// neighbour's twelve and its link).  Blocks of one colour share no site and
-// read only the other colour's data, so a sweep needs no synchronisation
-// between workgroups.
+// The block residual rho_B = eta_B - (D psi)_B is carried from visit to visit
+// rather than recomputed (Luescher's formulation of the procedure): after its
+// MR steps a block stores its MR residual R_B, and the next visit forms
+// rho_B = R_B - D_{B,dB} delta_dB, where delta_dB is the update that the
+// neighbouring blocks of the other colour made in between (on the first
+// visit R_B = eta_B).  The hops of delta arrive through face buffers that the
+// other colour published at the end of its solves (block_ops.h: six dense
+// components per boundary hop).  psi_B before the visit waits in the half of
+// the LDS exchange buffer that the in-wavefront directions leave free.
+// Blocks of one colour share no site and read only the other colour's data,
+// so a sweep needs no synchronisation between workgroups.
 //
 // k_sap_sweep_eo is the same sweep with the even-odd preconditioned block
 // solve (MR on the even-site Schur complement, odd sites reconstructed);
@@ -53,6 +57,7 @@ struct SArgs {
     const long *psi_off;
     const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
     int publish;          // write the face buffers for the next sweep
+    int write_r;          // plain sweep: store the block residual for the next visit
 };
 
 // The MR coefficient of one right-hand side: the dot products <q, r> and
@@ -96,13 +101,20 @@ template <typename A, typename RES> struct DelStore {
     cx<A> d[RES::clover_half ? 12 : 1][RES::clover_half ? BS : 1];
 };
 
+// Whether the plain sweep of storage type S carries the block residual.
+template <typename S> constexpr bool SAP_CARRY = !std::is_same<S, double>::value;
+
 template <typename S, typename A, typename RES>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
     const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
-    const vec2_t<S> *__restrict__ clov, vec2_t<S> *__restrict__ faces, SArgs a)
+    const vec2_t<S> *__restrict__ clov, vec2_t<S> *__restrict__ faces, vec2_t<S> *__restrict__ resid, SArgs a)
 {
     constexpr bool REGLINKS = RES::links;
     static_assert(REGLINKS, "the face buffers assume register-resident links");
+    static_assert(RES::clover_half, "the MR accumulator lives in LDS");
+    // FP32/FP16 storage carries the block residual between visits; FP64
+    // recomputes it (the carried form spills in FP64's register budget)
+    constexpr bool CARRY = SAP_CARRY<S>;
     __shared__ Lds<A> L;
     __shared__ DelStore<A, RES> D;
     const int i = xcd_remap(blockIdx.x, gridDim.x);
@@ -135,69 +147,87 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
         vec2_t<S> *__restrict__ psi = psi0 + (a.psi_off ? a.psi_off[r] : 0);
         const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
+        const long rp = ((long)b * a.nrhs + r) * 12 * BS + s; // the carried residual (no slot offsets)
         cx<A> rr[12], q[12];
-        // del = psi_B on entry; MR adds alpha * r to it
-        cx<A> del[RES::clover_half ? 1 : 12];
-        {
-            cx<A> d0[12];
+        vec2_t<S> er[12];
+        if constexpr (CARRY) {
+            // psi_B before this visit, in the half of the exchange buffer that
+            // the in-wavefront directions leave unused; delta starts at 0
             if (a.mode == 2) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) d0[c] = ldc<A>(psi + sp + c * BS);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 12; ++c) d0[c] = mk<A>(0, 0);
+                for (int c = 0; c < 12; ++c) {
+                    const cx<A> v = ldc<A>(psi + sp + c * BS);
+                    if (c < 6) L.hf[0][c][s] = v;
+                    else L.hb[0][c - 6][s] = v;
+                }
             }
-            // q = (D psi)_B: the block part, then the hops from the other colour
+#pragma unroll
+            for (int c = 0; c < 12; ++c) D.d[c][s] = mk<A>(0, 0);
+            // rho = R - (hops of the other colour's last update), R being this
+            // block's residual after its previous visit (eta on the first)
+            const vec2_t<S> *__restrict__ src = a.mode == 2 ? resid + rp : eta + sp;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) er[c] = src[c * BS];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+        } else {
+            // rho = eta - (D psi)_B, recomputed: the block part here, the hops
+            // of the other colour's psi below; delta starts at psi_B
+            cx<A> d0[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) d0[c] = a.mode == 2 ? ldc<A>(psi + sp + c * BS) : mk<A>(0, 0);
             if (a.mode == 2) {
                 block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, d0, q);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
             }
-            if constexpr (RES::clover_half) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) D.d[c][s] = d0[c];
-            } else {
+            for (int c = 0; c < 12; ++c) D.d[c][s] = d0[c];
+            // eta in flight during the face trips (held in the storage type)
 #pragma unroll
-                for (int c = 0; c < 12; ++c) del[c] = d0[c];
-            }
+            for (int c = 0; c < 12; ++c) er[c] = eta[sp + c * BS];
         }
-        // eta in flight during the face trips (held in the storage type)
-        vec2_t<S> er[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) er[c] = eta[sp + c * BS];
-        // the boundary hops, from the faces the other colour published
         if (a.mode != 0) face_consume<S, A>(a.g, b, bc, s, r, a.nrhs, faces, U, q);
-        // rho = eta - (D psi)_B
 #pragma unroll
         for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(&er[c]) - q[c];
-        // MR on D_BB
+        // MR on D_BB: delta += alpha r, r -= alpha q
         for (int it = 0; it < a.nmr; ++it) {
             block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
             cx<A> alpha;
             if (!mr_alpha(L, lane, wave, q, rr, alpha)) break;
-            // delta += alpha r, then r -= alpha q
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                if constexpr (RES::clover_half) {
-                    cx<A> d = D.d[c][s];
-                    cmac(d, alpha, rr[c]);
-                    D.d[c][s] = d;
-                } else {
-                    cmac(del[c], alpha, rr[c]);
-                }
+                cx<A> d = D.d[c][s];
+                cmac(d, alpha, rr[c]);
+                D.d[c][s] = d;
                 rr[c] = rr[c] - alpha * q[c];
             }
         }
         cx<A> fin[12];
+        if constexpr (CARRY) {
+            // psi_B += delta; the residual carried to the next visit; the
+            // faces of delta for the other colour
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            if constexpr (RES::clover_half) fin[c] = D.d[c][s];
-            else fin[c] = del[c];
-            vec2_t<S> v;
-            stc(&v, fin[c]);
-            psi[sp + c * BS] = v;
-            fin[c] = ldc<A>(&v); // the stored value, as the other colour would read it
+            for (int c = 0; c < 12; ++c) {
+                fin[c] = D.d[c][s];
+                cx<A> v = fin[c];
+                if (a.mode == 2) v = v + (c < 6 ? L.hf[0][c][s] : L.hb[0][c - 6][s]);
+                stc(psi + sp + c * BS, v);
+            }
+            if (a.write_r) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) stc(resid + rp + c * BS, rr[c]);
+            }
+        } else {
+            // psi_B = delta; the faces of psi as stored
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                vec2_t<S> v;
+                stc(&v, D.d[c][s]);
+                psi[sp + c * BS] = v;
+                fin[c] = ldc<A>(&v);
+            }
         }
         if (a.publish) face_publish<S, A>(faces, b, a.nrhs, r, s, fin, U);
     }
@@ -571,15 +601,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 }
 
 template <typename S, typename A, typename RES, bool EO>
-Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces)
+Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces, void *resid)
 {
-    // algorithmic traffic of one colour sweep: links + clover once, eta, psi
-    // (read only when nonzero) and psi written, per swept site and rhs
+    // algorithmic traffic of one colour sweep: links + clover once, eta (or
+    // the carried residual), psi (read only when nonzero), psi written and,
+    // in the plain form, the residual carried to the next visit
     const double sites = 256.0 * a.nblk, sb = (double)sizeof(S), n = a.nrhs;
-    const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0)));
-    // the even-odd form adds one in-block hop application (the right-hand
-    // side and the odd reconstruction) per block solve
-    const double fl = sites * n * (a.nmr * 2184.0 + (a.mode == 2 ? 1848.0 : 0.0) + (EO ? 1848.0 : 0.0));
+    constexpr bool CARRY = !EO && SAP_CARRY<S>;
+    const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0) +
+                                                      (CARRY && a.write_r ? 24.0 : 0.0)));
+    // recomputing the block residual costs one operator application when
+    // psi_B != 0; carrying it costs none.  The even-odd form adds one
+    // in-block hop application (the right-hand side and the odd
+    // reconstruction) per block solve.
+    const double fl = sites * n * (a.nmr * 2184.0 + (!CARRY && a.mode == 2 ? 1848.0 : 0.0) + (EO ? 1848.0 : 0.0));
     const int cls = EO ? (prec == DD_F64 ? K_SAP_EO_F64 : prec == DD_F32 ? K_SAP_EO_F32 : K_SAP_EO_F16)
                        : (prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16);
     ProfScope ps(ctx->prof, ctx->stream, cls, by, fl);
@@ -592,7 +627,7 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
         k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
             static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
-            static_cast<vec2_t<S> *>(faces), a);
+            static_cast<vec2_t<S> *>(faces), static_cast<vec2_t<S> *>(resid), a);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
@@ -610,11 +645,18 @@ typedef Residency<true, false, 1, true> ResEO;
 
 } // namespace
 
-Status reserve_sap_faces(dd_ctx *ctx, int prec, int nrhs)
+size_t sap_scratch_bytes(const GeomHost &g, int prec, int nrhs)
 {
-    const size_t need = spinor_bytes(ctx->g, prec, nrhs); // FACE_ELEMS = 12 * BS per block and rhs
-    if (ctx->sap_faces.p && ctx->sap_faces.bytes >= need) return Status::ok();
-    return ctx->sap_faces.alloc(need);
+    // face buffers (FACE_ELEMS = 12 * BS per block and rhs) and the carried
+    // block residual: one spinor each
+    return 2 * spinor_bytes(g, prec, nrhs);
+}
+
+Status reserve_sap_scratch(dd_ctx *ctx, int prec, int nrhs)
+{
+    const size_t need = sap_scratch_bytes(ctx->g, prec, nrhs);
+    if (ctx->sap_scratch.p && ctx->sap_scratch.bytes >= need) return Status::ok();
+    return ctx->sap_scratch.alloc(need);
 }
 
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
@@ -643,13 +685,15 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
         a.psi_off = slots->psi_off;
         a.active = slots->active;
     }
-    // face buffers: the caller's, else the context's
-    void *faces = slots ? slots->faces : nullptr;
-    if (!faces) {
-        DD_TRY(reserve_sap_faces(ctx, prec, nrhs));
-        faces = ctx->sap_faces.p;
+    // face buffers and carried residual: the caller's scratch, else the context's
+    void *scratch = slots ? slots->scratch : nullptr;
+    if (!scratch) {
+        DD_TRY(reserve_sap_scratch(ctx, prec, nrhs));
+        scratch = ctx->sap_scratch.p;
     }
-    if (!faces) return Status{DD_INVALID_ARG, "SAP: no face buffer"};
+    if (!scratch) return Status{DD_INVALID_ARG, "SAP: no scratch buffer"};
+    void *faces = scratch;
+    void *resid = static_cast<char *>(scratch) + spinor_bytes(ctx->g, prec, nrhs);
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;
@@ -657,14 +701,15 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
             a.nblk = ctx->ncolour[col];
             a.mode = (cy == 0 && col == 0) ? 0 : (cy == 0 ? 1 : 2);
             a.publish = !(cy == ncy - 1 && col == 1);
+            a.write_r = cy < ncy - 1;
             if (eo) {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi, faces)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi, faces)));
-                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
+                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
             } else {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces)));
-                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces, resid)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces, resid)));
+                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces, resid)));
             }
         }
     return Status::ok();
