@@ -34,8 +34,10 @@ def lat(request):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("ncy,nmr", [(1, 4), (3, 2), (2, 0)])
+@pytest.mark.parametrize("ncy,nmr", [(1, 4), (3, 2), (2, 0), (4, 4)])
 def test_sap_matches_oracle(lat, prec, ncy, nmr):
+    """(4, 4) is the production setting: with FP32/FP16 storage every block
+    is visited four times, three of them with the carried residual."""
     eta = synth.gaussian_spinor(lat.dims, seed=3)
     m0 = -0.2
     ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0, eta, ncy, nmr, BC)
@@ -51,8 +53,11 @@ def test_sap_zero_cycles_is_zero(lat):
     assert np.max(np.abs(out)) == 0
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_sap_multi_rhs(lat, prec):
+    """Three right-hand sides with their own masses, then each alone: the
+    context's smoother scratch (faces, carried residual) is reused across
+    calls of different width."""
     n = 3
     eta = synth.gaussian_spinor(lat.dims, nrhs=n, seed=5)
     m0 = np.array([-0.3, -0.1, 0.2])
@@ -60,8 +65,8 @@ def test_sap_multi_rhs(lat, prec):
     for r in range(n):
         ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0[r], eta[r], 2, 4, BC)
         assert rel(out[r], ref) <= REL_TOL_SAP[prec]
-        if prec == "f64":
-            assert np.array_equal(out[r], gpu_sap(lat, eta[r], m0[r], 2, 4, prec))
+        # each right-hand side runs the same instruction sequence alone
+        assert np.array_equal(out[r], gpu_sap(lat, eta[r], m0[r], 2, 4, prec))
 
 
 def gpu_solve(lat, b, m0, sap_prec, nrhs=None, **kw):
