@@ -206,14 +206,15 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
     if constexpr (RES::clover) {
         clover_mac(cl, diag, v, q);
     } else if constexpr (RES::clover_half) {
-        clover_half_mac<A>(cl, diag, v, q);
         cx<A> c2[18];
         const vec2_t<S> *cp = clov_g + ((long)b * 36 + 18) * BS + s;
         // the address is the same at every MR step: hide that, or the loads
         // are hoisted out of the MR loop and the half is held in registers
         asm volatile("" : "+v"(cp));
+        // half 1's loads are in flight while half 0 (registers) is applied
 #pragma unroll
         for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
+        clover_half_mac<A>(cl, diag, v, q);
         clover_half_mac<A>(c2, diag, v + 6, q + 6);
     } else {
 #pragma unroll 1
@@ -401,10 +402,32 @@ __device__ __forceinline__ void face_consume(const Geom &g, int b, const int bc[
     }
 }
 
+// One DPP step of the wavefront sum: v + (v moved by ctrl), with rows outside
+// row_mask (and invalid source lanes) adding zero.
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_add(double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xf, true);
+    return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order, with cross-lane DPP
+// moves (no LDS round trips): pairs, quads, half rows and rows of 16, then
+// row 1 += row 0 and row 3 += row 2 (row_bcast:15), then rows 2-3 += the
+// first half (row_bcast:31).  The total is valid in lane 63 only.
 template <typename A> __device__ __forceinline__ A wave_sum(A v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = dpp_add<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v); // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v); // row_mirror
+    v = dpp_add<0x142, 0xa>(v); // row_bcast:15
+    v = dpp_add<0x143, 0xc>(v); // row_bcast:31
     return v;
 }
 

@@ -61,9 +61,9 @@ struct SArgs {
 };
 
 // The MR coefficient of one right-hand side: the dot products <q, r> and
-// <q, q> over the block (wavefront shuffles, then a fixed-order combine of the
-// four wavefronts through LDS), alpha = <q, r>/<q, q>; returns false when
-// <q, q> vanishes (uniform over the workgroup).
+// <q, q> over the block (DPP sums within each wavefront, then a fixed-order
+// combine of the four wavefronts through LDS), alpha = <q, r>/<q, q>; returns
+// false when <q, q> vanishes (uniform over the workgroup).
 template <typename A>
 __device__ __forceinline__ bool mr_alpha(Lds<A> &L, int lane, int wave, const cx<A> q[12], const cx<A> rr[12],
                                          cx<A> &alpha)
@@ -81,7 +81,7 @@ __device__ __forceinline__ bool mr_alpha(Lds<A> &L, int lane, int wave, const cx
     qr_re = wave_sum(qr_re);
     qr_im = wave_sum(qr_im);
     qq = wave_sum(qq);
-    if (lane == 0) {
+    if (lane == 63) { // where wave_sum leaves the total
         L.red[wave][0] = qr_re;
         L.red[wave][1] = qr_im;
         L.red[wave][2] = qq;
