@@ -11,18 +11,22 @@
 //     and chiral half 0 of its clover term live in registers for the whole
 //     sweep and every right-hand side; clover half 1 is re-read at each block
 //     application and stays in L2; the MR accumulator lives in LDS;
-//   * D_BB is applied direction by direction: each thread publishes the
+//   * D_BB is applied direction by direction: each thread provides the
 //     spin-projected half spinor of its site for the +mu hop of site x-mu and
-//     U_mu(x)^+ times the projected half spinor for the -mu hop of site x+mu
-//     through LDS, so no spinor leaves the chip inside the MR loop;
-//   * the two block dot products per MR step reduce with wavefront shuffles
-//     and a fixed-order combine of the four wavefronts (deterministic).
+//     U_mu(x)^+ times the projected half spinor for the -mu hop of site x+mu,
+//     across lanes of its wavefront for x, y, z (a wavefront is one t-slice)
+//     and through LDS for t, so no spinor leaves the chip inside the MR loop;
+//   * the two block dot products per MR step reduce with DPP sums within each
+//     wavefront and a fixed-order combine of the four wavefronts
+//     (deterministic).
 // eta and psi go through the caches (they are re-read by the next sweep and
 // by the operator that follows the smoother, and fit in the 256 MB
 // last-level cache in FP32); links and clover half 0, read once per sweep,
 // stream.
-// The block residual rho_B = eta_B - (D psi)_B is carried from visit to visit
-// rather than recomputed (Luescher's formulation of the procedure): after its
+// With FP32/FP16 storage the block residual rho_B = eta_B - (D psi)_B is
+// carried from visit to visit rather than recomputed (FP64 recomputes it: the
+// carried form does not fit its register budget as well).  Luescher's
+// formulation of the procedure: after its
 // MR steps a block stores its MR residual R_B, and the next visit forms
 // rho_B = R_B - D_{B,dB} delta_dB, where delta_dB is the update that the
 // neighbouring blocks of the other colour made in between (on the first
