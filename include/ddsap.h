@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define DD_ABI_VERSION 2
+#define DD_ABI_VERSION 3
 #define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
 
 typedef enum {
@@ -129,8 +129,22 @@ dd_status dd_synchronize(dd_ctx *ctx);
 /* Setup (not timed): copy the canonical FP64 gauge field U (host pointer,
  * 72*V doubles), build the clover term with coefficient csw on the device in
  * FP64, and store links and clover in the blocked layout in FP64, FP32 and
- * FP16.  Synchronises.  DD_NAN if U holds NaN/Inf. */
+ * FP16.  Synchronises.  DD_NAN if U holds NaN/Inf.  When every link is in
+ * SU(3) to within 1e-13 (max |U U^+ - 1| and |det U - 1|), gauge compression
+ * is switched on (see dd_set_link_compression). */
 dd_status dd_set_gauge(dd_ctx *ctx, const double *U_host, double csw);
+
+/* Gauge compression ("reconstruct-12"): the operator and smoother kernels
+ * read the first two rows of each link and rebuild the third as the complex
+ * conjugate of their cross product, which holds for SU(3) matrices; this cuts
+ * the link bytes per site from 72 to 48 reals.  enable = 0 switches it off
+ * (all nine entries are read); enable = 1 switches it on, DD_INVALID_ARG if
+ * the current field is not SU(3) (or none is set).  Applies to calls made
+ * afterwards; servers and solves capture it when their engines are built. */
+dd_status dd_set_link_compression(dd_ctx *ctx, int enable);
+
+/* 1 if gauge compression is on, 0 if off, -1 for a NULL context. */
+int dd_link_compression(const dd_ctx *ctx);
 
 /* Replace the clover term by an explicit one (host pointer, canonical clover
  * layout, 144*V doubles; each 6x6 half must be Hermitian, only its upper

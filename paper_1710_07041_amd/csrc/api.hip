@@ -191,6 +191,17 @@ dd_status dd_set_gauge(dd_ctx *ctx, const double *U_host, double csw)
     });
 }
 
+dd_status dd_set_link_compression(dd_ctx *ctx, int enable)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (enable && !(ctx->has_field && ctx->link_su3))
+        return fail(ctx, DD_INVALID_ARG, "dd_set_link_compression: the gauge field is not SU(3)");
+    ctx->link_r12 = enable != 0;
+    return DD_OK;
+}
+
+int dd_link_compression(const dd_ctx *ctx) { return ctx ? (ctx->link_r12 ? 1 : 0) : -1; }
+
 dd_status dd_set_clover(dd_ctx *ctx, const double *C_host)
 {
     if (!ctx) return DD_INVALID_ARG;

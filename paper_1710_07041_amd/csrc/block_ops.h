@@ -276,7 +276,7 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
 template <typename SP, typename S, typename A, bool REGLINKS>
 __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4], int s, int r, int nrhs,
                                           const vec2_t<SP> *__restrict__ psi, const vec2_t<S> *__restrict__ links,
-                                          const cx<A> Ur[REGLINKS ? 4 : 1][9], cx<A> q[12])
+                                          const cx<A> Ur[REGLINKS ? 4 : 1][9], cx<A> q[12], bool r12)
 {
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
@@ -294,9 +294,7 @@ __device__ __forceinline__ void face_hops(const Geom &g, int b, const int bc[4],
         if (!REGLINKS || dir < 0) {
             // issued before either branch's arithmetic waits on p
             const int lb = dir > 0 ? b : bn, ls = dir > 0 ? s : sn;
-            const vec2_t<S> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+            load_link<A>(links + ((long)lb * 4 + mu) * 9 * BS + ls, r12, U);
         } else {
             // explicit branches: a switch would become a dynamic register index
             if (mu == 0) { for (int e = 0; e < 9; ++e) U[e] = Ur[0][e]; }

@@ -144,6 +144,59 @@ template <typename A, typename T> __device__ __forceinline__ void stc_stream(T *
 }
 
 // ---------------------------------------------------------------------------
+// Links.  One link is nine complex entries U[3 row + col], BS apart in the
+// blocked layout.  With r12 (gauge compression, "reconstruct-12") only the
+// first two rows are read and the third is the complex conjugate of their
+// cross product, which is exact for SU(3) matrices (orthonormal rows,
+// determinant 1); the context enables it only for fields that are SU(3) to
+// FP64 rounding.
+template <typename A> __device__ __forceinline__ void su3_third_row(cx<A> U[9])
+{
+    U[6] = conjx(U[1] * U[5] - U[2] * U[4]);
+    U[7] = conjx(U[2] * U[3] - U[0] * U[5]);
+    U[8] = conjx(U[0] * U[4] - U[1] * U[3]);
+}
+// The four links of a site (u: entry 0 of link mu = 0; links mu are 9 BS
+// apart), times k: all loads are issued before any third row is rebuilt, so
+// they are in flight together.
+template <typename A, bool NT = false, typename T>
+__device__ __forceinline__ void load_links4(const T *u, bool r12, A k, cx<A> U[4][9])
+{
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            U[mu][e] = NT ? ldc_stream<A>(u + (mu * 9 + e) * BS) : ldc<A>(u + (mu * 9 + e) * BS);
+    if (r12) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) su3_third_row(U[mu]);
+    } else {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int e = 6; e < 9; ++e)
+                U[mu][e] = NT ? ldc_stream<A>(u + (mu * 9 + e) * BS) : ldc<A>(u + (mu * 9 + e) * BS);
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[mu][e] = k * U[mu][e];
+}
+
+template <typename A, bool NT = false, typename T>
+__device__ __forceinline__ void load_link(const T *u, bool r12, cx<A> U[9])
+{
+#pragma unroll
+    for (int e = 0; e < 6; ++e) U[e] = NT ? ldc_stream<A>(u + e * BS) : ldc<A>(u + e * BS);
+    if (r12) {
+        su3_third_row(U);
+    } else {
+#pragma unroll
+        for (int e = 6; e < 9; ++e) U[e] = NT ? ldc_stream<A>(u + e * BS) : ldc<A>(u + e * BS);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // chiral-basis spin projection.  g_mu = [[0, A_mu], [A_mu^+, 0]] with
 // A_k = -i sigma_k (k = x, y, z) and A_t = 1.  For psi = (u, l) (upper spins
 // 0-1, lower spins 2-3):

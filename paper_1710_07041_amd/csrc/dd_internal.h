@@ -122,6 +122,8 @@ struct dd_ctx {
     int device = 0;
     bool has_field = false;
     double csw = 0;
+    bool link_su3 = false; // every link is SU(3) to FP64 rounding (checked at ingest)
+    bool link_r12 = false; // kernels read two rows per link and rebuild the third
     dd::DevBuf links[3];  // blocked links per dd_prec
     dd::DevBuf clover[3]; // blocked clover per dd_prec
     dd::DevBuf colour_blocks[2]; // int block ids of each colour, XCD-friendly order
@@ -138,6 +140,8 @@ size_t real_bytes(int prec); // 8, 4, 2
 size_t spinor_bytes(const GeomHost &g, int prec, int nrhs);
 
 // fields.hip
+// Packs the links (and builds the clover term) in every precision and checks
+// whether all links are SU(3) to within 1e-13 (then link_su3 and link_r12).
 Status build_fields(dd_ctx *ctx, const double *U_dev_canon, double csw);
 Status set_clover_canon(dd_ctx *ctx, const double *C_dev_canon);
 Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs);

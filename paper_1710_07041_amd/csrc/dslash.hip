@@ -32,6 +32,7 @@ struct DArgs {
     const double *m0_dev; // per-rhs masses in device memory (overrides m0 when set)
     const long *in_off;   // per-rhs element offset added to the input (nullable)
     const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
+    int r12;              // links stored as SU(3): read two rows, rebuild the third
 };
 
 // One hop of direction index k = 2 mu + (0: forward, 1: backward) onto acc.
@@ -97,13 +98,11 @@ __device__ __forceinline__ void hop_switch(int k, const vec2_t<SI> *__restrict__
 
 template <typename SF, typename A>
 __device__ __forceinline__ void load_hop_link(const vec2_t<SF> *__restrict__ links, int b, int s, int k, int bn,
-                                              int sn, cx<A> U[9])
+                                              int sn, bool r12, cx<A> U[9])
 {
     const int mu = k >> 1;
     const int lb = (k & 1) ? bn : b, ls = (k & 1) ? sn : s;
-    const vec2_t<SF> *u = links + ((long)lb * 4 + mu) * 9 * BS + ls;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) U[e] = ldc<A>(u + e * BS);
+    load_link<A>(links + ((long)lb * 4 + mu) * 9 * BS + ls, r12, U);
 }
 
 template <bool BLOCKONLY, bool PF, bool PAIR, int RT, typename SI, typename SF, typename A>
@@ -129,10 +128,10 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
             const vec2_t<SI> *qb = in + ro[0] + ((long)bb * a.nrhs + r0) * 12 * BS + sb;
 #pragma unroll
             for (int c = 0; c < 12; ++c) pf[c] = qf[c * BS];
-            load_hop_link<SF, A>(links, b, s, 2 * mu, bf, sf, Uf);
+            load_hop_link<SF, A>(links, b, s, 2 * mu, bf, sf, a.r12, Uf);
 #pragma unroll
             for (int c = 0; c < 12; ++c) pb[c] = qb[c * BS];
-            load_hop_link<SF, A>(links, b, s, 2 * mu + 1, bb, sb, Ub);
+            load_hop_link<SF, A>(links, b, s, 2 * mu + 1, bb, sb, a.r12, Ub);
             cx<A> psi[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&pf[c]);
@@ -157,7 +156,7 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
         bool inb;
         neighbour_rt(a.g, b, bc, s, 0, +1, bn, sn, sign, inb);
         cx<A> U[9];
-        load_hop_link<SF, A>(links, b, s, 0, bn, sn, U);
+        load_hop_link<SF, A>(links, b, s, 0, bn, sn, a.r12, U);
 #pragma unroll 1
         for (int k = 0; k < 8; ++k) {
             const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
@@ -167,7 +166,7 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
             if (k < 7) { // uniform
                 const int k2 = k + 1;
                 neighbour_rt(a.g, b, bc, s, k2 >> 1, (k2 & 1) ? -1 : 1, bn2, sn2, sign2, inb);
-                load_hop_link<SF, A>(links, b, s, k2, bn2, sn2, Un);
+                load_hop_link<SF, A>(links, b, s, k2, bn2, sn2, a.r12, Un);
             }
             hop_switch<RT, SI, A>(k, p, ro, U, kk, acc);
 #pragma unroll
@@ -186,7 +185,7 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
             if (BLOCKONLY && !inb) continue;
             const vec2_t<SI> *p = in + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
             cx<A> U[9];
-            load_hop_link<SF, A>(links, b, s, k, bn, sn, U);
+            load_hop_link<SF, A>(links, b, s, k, bn, sn, a.r12, U);
             hop_switch<RT, SI, A>(k, p, ro, U, (A)(-0.5 * sign), acc);
         }
     }
@@ -294,14 +293,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     block_coords(a.g, b, bc);
     // register-resident links carry the hop factor -1/2
     cx<A> U[RES::links ? 4 : 1][9];
-    if (RES::links) {
-#pragma unroll
-        for (int mu = 0; mu < (RES::links ? 4 : 1); ++mu) {
-            const vec2_t<SF> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc<A>(u + e * BS);
-        }
-    }
+    if constexpr (RES::links) load_links4<A>(links + (long)b * 4 * 9 * BS + s, a.r12, (A)(-0.5), U);
     cx<A> cl[RES::clover ? 36 : 1];
     if (RES::clover) {
         const vec2_t<SF> *cp = clov + (long)b * 36 * BS + s;
@@ -317,7 +309,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = ldc<A>(inr + sp + c * BS);
         block_apply<SF, A, RES, NTC>(L, a.g, b, bc, s, U, cl, links, clov, diag, v, q);
-        face_hops<SI, SF, A, RES::links>(a.g, b, bc, s, r, a.nrhs, inr, links, U, q);
+        face_hops<SI, SF, A, RES::links>(a.g, b, bc, s, r, a.nrhs, inr, links, U, q, a.r12);
         if (RESID) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - q[c]);
@@ -338,6 +330,7 @@ DArgs make_args(const dd_ctx *ctx, const double *m0, int nrhs)
     }
     a.g.nblocks = ctx->g.nblocks;
     a.nrhs = nrhs;
+    a.r12 = ctx->link_r12 ? 1 : 0;
     for (int r = 0; r < nrhs && r < MAXRHS && m0; ++r) a.m0[r] = m0[r];
     return a;
 }
@@ -370,6 +363,9 @@ template <typename SI, typename SO, typename SF, typename A, bool RESID>
 Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_prec, const void *resid)
 {
     const double V = (double)ctx->g.V, n = a.nrhs;
+    // the method's data volume: links (72 reals per site) + clover (72) once,
+    // input and output spinors per right-hand side; with gauge compression the
+    // kernel reads 48 of the 72 link reals, which this figure does not count
     const double by = V * (144.0 * sizeof(SF) + 24.0 * n * (sizeof(SI) + sizeof(SO) * (RESID ? 2 : 1)));
     int cls = sizeof(SF) == 8 ? (sizeof(SI) == 8 ? K_DSLASH_F64 : K_DSLASH_F32IN_F64)
                               : (sizeof(SF) == 4 ? K_DSLASH_F32 : K_DSLASH_F16);

@@ -971,7 +971,8 @@ Status Engine::launch_step()
     const int bucket = pick_bucket(jmax);
     const bool use_graph = e.P.graphs && !e.ctx->prof.on;
     if (use_graph) {
-        const int key = bucket * 4 + e.sap_prec;
+        // the kernels' arguments also depend on the link format
+        const int key = (bucket * 4 + e.sap_prec) * 2 + (e.ctx->link_r12 ? 1 : 0);
         auto it = e.graphs.find(key);
         if (it == e.graphs.end()) {
             hipGraph_t g = nullptr;

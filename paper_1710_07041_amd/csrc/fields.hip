@@ -12,6 +12,9 @@
 // with B = (F_yz, F_zx, F_xy) and E_k = F_kt.  This is the form evaluated
 // below; it is derived here from the gamma algebra, not taken from the CPU
 // reference code.
+#include <algorithm>
+#include <vector>
+
 #include "dd_device.h"
 #include "dd_internal.h"
 
@@ -20,6 +23,9 @@ namespace dd {
 namespace {
 
 constexpr int TPB = 256;
+// largest deviation from SU(3) at which gauge compression is enabled: the
+// rebuilt third row then differs from the stored one by about this much
+constexpr double SU3_TOL = 1e-13;
 
 struct CanonGeom {
     int L[4];
@@ -187,6 +193,39 @@ __global__ __launch_bounds__(TPB) void k_links_pack(const double2 *__restrict__ 
         for (int e = 0; e < 9; ++e) stc(out + (((long)b * 4 + mu) * 9 + e) * BS + s, ldc<double>(U + (x * 4 + mu) * 9 + e));
 }
 
+// Largest deviation of a link from SU(3) in each block: max over the block's
+// sites and directions of max_ij |(U U^+ - 1)_ij| and |det U - 1| (FP64).
+__global__ __launch_bounds__(TPB) void k_su3_deviation(const double2 *__restrict__ U, double *__restrict__ out,
+                                                       CanonGeom g, int nblocks)
+{
+    __shared__ double red[TPB / 64];
+    const int b = blockIdx.x, s = threadIdx.x;
+    if (b >= nblocks) return; // uniform over the workgroup
+    const long x = canon_site(g, b, s);
+    double dev = 0.0;
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<double> u[9];
+        for (int e = 0; e < 9; ++e) u[e] = ldc<double>(U + (x * 4 + mu) * 9 + e);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                cx<double> m = mk(i == j ? -1.0 : 0.0, 0.0);
+                for (int k = 0; k < 3; ++k) cmacc(m, u[j * 3 + k], u[i * 3 + k]); // += u_ik conj(u_jk)
+                dev = fmax(dev, fmax(fabs(m.re), fabs(m.im)));
+            }
+        const cx<double> det = u[0] * (u[4] * u[8] - u[5] * u[7]) - u[1] * (u[3] * u[8] - u[5] * u[6]) +
+                               u[2] * (u[3] * u[7] - u[4] * u[6]);
+        dev = fmax(dev, hypot(det.re - 1.0, det.im));
+    }
+    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+    if ((s & 63) == 0) red[s >> 6] = dev;
+    __syncthreads();
+    if (s == 0) {
+        double m = red[0];
+        for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[w]);
+        out[b] = isfinite(m) ? m : 1e300;
+    }
+}
+
 // elementwise complex conversion FP64 -> S (round to nearest even)
 template <typename S>
 __global__ __launch_bounds__(TPB) void k_convert_from64(const double2 *__restrict__ in, vec2_t<S> *__restrict__ out,
@@ -292,6 +331,18 @@ Status build_fields(dd_ctx *ctx, const double *U_dev, double csw)
     DD_HIP_TRY(hipGetLastError());
     DD_TRY(convert_field(ctx->stream, ctx->clover[DD_F64].as<double2>(), ctx->clover[DD_F32].p, DD_F32, nc));
     DD_TRY(convert_field(ctx->stream, ctx->clover[DD_F64].as<double2>(), ctx->clover[DD_F16].p, DD_F16, nc));
+    // gauge compression applies when every link is SU(3) to FP64 rounding
+    DevBuf dev;
+    DD_TRY(dev.alloc((size_t)g.nblocks * sizeof(double)));
+    k_su3_deviation<<<g.nblocks, TPB, 0, ctx->stream>>>(U, dev.as<double>(), cg, g.nblocks);
+    DD_HIP_TRY(hipGetLastError());
+    std::vector<double> hdev(g.nblocks);
+    DD_HIP_TRY(hipMemcpyAsync(hdev.data(), dev.p, hdev.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    double worst = 0.0;
+    for (double d : hdev) worst = std::max(worst, d);
+    ctx->link_su3 = worst <= SU3_TOL;
+    ctx->link_r12 = ctx->link_su3;
     return Status::ok();
 }
 

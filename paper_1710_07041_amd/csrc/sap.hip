@@ -61,6 +61,7 @@ struct SArgs {
     const long *psi_off;
     const int *active;    // right-hand sides with active[r] == 0 are skipped (nullable)
     int publish;          // write the face buffers for the next sweep
+    int r12;              // links stored as SU(3): read two rows, rebuild the third
     int write_r;          // plain sweep: store the block residual for the next visit
 };
 
@@ -129,15 +130,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     block_coords(a.g, b, bc);
 
     // register-resident links carry the hop factor -1/2
-    cx<A> U[REGLINKS ? 4 : 1][9];
-    if (REGLINKS) {
-#pragma unroll
-        for (int mu = 0; mu < (REGLINKS ? 4 : 1); ++mu) {
-            const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc_stream<A>(u + e * BS);
-        }
-    }
+    cx<A> U[4][9];
+    load_links4<A, true>(links + (long)b * 4 * 9 * BS + s, a.r12, (A)(-0.5), U);
     cx<A> cl[RES::ncl];
     if (RES::clover || RES::clover_half) {
         const vec2_t<S> *cp = clov + (long)b * 36 * BS + s;
@@ -436,12 +430,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 
     // register-resident links carry the hop factor -1/2
     cx<A> U[4][9];
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const vec2_t<S> *u = links + ((long)b * 4 + mu) * 9 * BS + s;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) U[mu][e] = (A)(-0.5) * ldc_stream<A>(u + e * BS);
-    }
+    load_links4<A, true>(links + (long)b * 4 * 9 * BS + s, a.r12, (A)(-0.5), U);
     const vec2_t<S> *cp0 = clov + (long)b * 36 * BS + s;
 
     for (int r = 0; r < a.nrhs; ++r) {
@@ -491,7 +480,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 #pragma unroll
             for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(&er[c]) - q[c];
         } else {
-            if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q);
+            if (a.mode != 0) face_hops<S, S, A, true>(a.g, b, bc, s, r, a.nrhs, psi, links, U, q, a.r12);
 #pragma unroll
             for (int c = 0; c < 12; ++c) rho[c] = ldc<A>(eta + sp + c * BS) - q[c];
         }
@@ -612,6 +601,7 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
     // in the plain form, the residual carried to the next visit
     const double sites = 256.0 * a.nblk, sb = (double)sizeof(S), n = a.nrhs;
     constexpr bool CARRY = !EO && SAP_CARRY<S>;
+    // (links count 72 reals per site also when compressed: the method's volume)
     const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0) +
                                                       (CARRY && a.write_r ? 24.0 : 0.0)));
     // recomputing the block residual costs one operator application when
@@ -682,6 +672,7 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
     a.g.nblocks = ctx->g.nblocks;
     a.nrhs = nrhs;
     a.nmr = nmr;
+    a.r12 = ctx->link_r12 ? 1 : 0;
     for (int r = 0; r < nrhs && m0; ++r) a.m0[r] = m0[r];
     if (slots) {
         a.m0_dev = slots->m0_dev;

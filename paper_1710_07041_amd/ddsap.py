@@ -37,7 +37,7 @@ DD_MAX_RHS = 16
 
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
-    "dd_set_gauge", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
+    "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
     "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_profile_enable", "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
@@ -86,6 +86,8 @@ _sigs = {
     "dd_synchronize": ([_vp], _i),
     "dd_set_gauge": ([_vp, _vp, _d], _i),
     "dd_set_clover": ([_vp, _vp], _i),
+    "dd_set_link_compression": ([_vp, _i], _i),
+    "dd_link_compression": ([_vp], _i),
     "dd_spinor_bytes": ([_vp, _i, _i], _sz),
     "dd_pack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
     "dd_unpack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
@@ -183,6 +185,15 @@ class Context:
         if U.size != self.volume * 36:
             raise ValueError("gauge field has the wrong size")
         self._check(_lib.dd_set_gauge(self._h, _vp(U.ctypes.data), float(csw)))
+
+    def set_link_compression(self, enable):
+        """dd_set_link_compression: read two rows per link and rebuild the
+        third (SU(3) fields only)."""
+        self._check(_lib.dd_set_link_compression(self._h, 1 if enable else 0))
+
+    @property
+    def link_compression(self) -> bool:
+        return _lib.dd_link_compression(self._h) == 1
 
     def set_clover(self, C):
         """C: host complex128 array (V, 2, 6, 6): the two chiral 6x6 halves."""

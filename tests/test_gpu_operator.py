@@ -109,6 +109,54 @@ def test_explicit_clover_roundtrip():
     assert rel(before, oracle.apply_D(dims, lat.U, C, 0.1, psi, BC)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_link_compression_matches_full_links(lat, prec):
+    """The synthetic links are SU(3), so the context reads two rows per link and
+    rebuilds the third; the result equals the one with all nine entries read
+    up to rounding, and both match the oracle."""
+    assert lat.ctx.link_compression
+    psi = synth.gaussian_spinor(lat.dims, seed=7)
+    m0 = -0.25
+    on = lat.apply(psi, m0, prec)
+    lat.ctx.set_link_compression(False)
+    try:
+        assert not lat.ctx.link_compression
+        off = lat.apply(psi, m0, prec)
+    finally:
+        lat.ctx.set_link_compression(True)
+    tol = {"f64": 1e-13, "f32": 1e-6, "f16": 2e-3}[prec]
+    assert rel(on, off) <= tol
+    ref = oracle.apply_D(lat.dims, lat.U, lat.C, m0, psi, BC)
+    assert rel(off, ref) <= REL_TOL_APPLY[prec]
+
+
+def test_link_compression_needs_su3():
+    """A field that is not SU(3) keeps all nine entries per link; asking for
+    compression is an error, and the operator still matches the oracle."""
+    from paper_1710_07041_amd import ddsap
+    dims = (8, 4, 4, 8)
+    U = synth.random_su3_links(dims, 0.4, seed=3)
+    U[5, 2] *= 1.001  # one link off the group
+    ctx = ddsap.Context(dims, BC)
+    ctx.set_gauge(U, 1.0)
+    assert not ctx.link_compression
+    with pytest.raises(ddsap.DDError) as e:
+        ctx.set_link_compression(True)
+    assert e.value.status == ddsap.DD_INVALID_ARG
+    import torch
+    psi = synth.gaussian_spinor(dims, seed=8)
+    x = to_dev(psi)
+    xb = ctx.empty_blocked("f64")
+    yb = ctx.empty_blocked("f64")
+    ctx.pack(x, xb, "f64")
+    ctx.apply_D(-0.2, xb, yb, "f64")
+    y = torch.empty_like(x)
+    ctx.unpack(yb, y, "f64")
+    ctx.synchronize()
+    C = oracle.clover_field(dims, U, 1.0)
+    assert rel(to_host(y), oracle.apply_D(dims, U, C, -0.2, psi, BC)) <= REL_TOL_APPLY["f64"]
+
+
 def test_free_field_plane_wave_gpu():
     """Unit links: the GPU operator reproduces the closed form directly."""
     from dense_ref import gammas

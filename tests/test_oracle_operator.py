@@ -113,6 +113,17 @@ def test_links_are_su3(rand_field):
     assert np.max(np.abs(np.linalg.det(U) - 1)) < 1e-13
 
 
+def test_su3_third_row_is_conjugate_cross_product(rand_field):
+    """The identity behind gauge compression: for U in SU(3) the third row is
+    the complex conjugate of the cross product of the first two.  A general
+    unitary matrix (determinant a phase) breaks it by that phase."""
+    dims, U = rand_field
+    row2 = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    assert np.max(np.abs(row2 - U[..., 2, :])) < 1e-13
+    W = U * np.exp(1j * 0.3 / 3)  # det W = exp(0.3 i)
+    assert np.max(np.abs(np.conj(np.cross(W[..., 0, :], W[..., 1, :])) - W[..., 2, :])) > 0.1
+
+
 def test_clover_symmetries(rand_field):
     """C(x) Hermitian, commutes with gamma5, and is traceless (spin trace of sigma vanishes)."""
     dims, U = rand_field
