@@ -244,8 +244,9 @@ def serve_main(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver does not shard across GPUs "
-              "in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver does not shard a lattice "
+              "across GPUs (the domain decomposition over several GPUs is designed, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve_main(args)
