@@ -111,11 +111,13 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
                                      cx<A> acc[RT][12])
 {
     if constexpr (PAIR && !BLOCKONLY && RT == 1 && sizeof(SI) <= 4) {
-        // FP32 or FP16 input, one right-hand side: both hops of a direction
-        // in one trip, so the link that site x - mu reads for its forward hop
-        // is re-read for the backward hop of site x at once (from L1) rather
+        // FP32 input, one right-hand side: both hops of a direction in one
+        // trip, so the link that site x - mu reads for its forward hop is
+        // re-read for the backward hop of site x at once (from L1) rather
         // than a trip later (with FP64 input the pair does not fit in
-        // registers; that form loads the next hop's link one trip ahead)
+        // registers, and FP16 input runs faster at four waves per SIMD,
+        // where the pair spills; those forms load the next hop's link one
+        // trip ahead)
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             int bf, sf, gf, bb, sb, gb;
@@ -192,32 +194,52 @@ __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const ve
 }
 
 // occupancy target per precision: enough waves per SIMD to keep HBM busy
-// without letting the scheduler hoist all eight hops' loads at once
-template <typename A, int RT> struct DslashWaves { static constexpr int value = RT > 1 ? 2 : 3; };
-template <int RT> struct DslashWaves<double, RT> { static constexpr int value = 2; };
+// without letting the scheduler hoist all eight hops' loads at once (FP16
+// input, one right-hand side per lane: four, with the link-prefetch form)
+template <typename SI, typename A, int RT> struct DslashWaves {
+    static constexpr int value = sizeof(A) == 8 ? 2 : (RT > 1 ? 2 : (sizeof(SI) == 2 ? 4 : 3));
+};
 
 // One 256-thread workgroup per (block, group of RT right-hand sides); the
 // groups of one block follow each other in the launch order, so the block's
 // links and clover terms are re-read from L2.  Streaming clover loads (NTC)
 // only when a block has a single group.
-template <typename SI, typename SO, typename SF, typename A, bool BLOCKONLY, bool RESID, int RT, bool NTC>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<A, RT>::value))) void k_dslash(const vec2_t<SI> *__restrict__ in, vec2_t<SO> *__restrict__ out,
+// With G > 1 (and RT == 1) G lanes of a wavefront share a site: a wavefront
+// covers 64/G sites for G right-hand sides, so every link and clover load of
+// the wavefront serves G right-hand sides at once (a group of G right-hand
+// sides takes G workgroups per block, of 256/G sites each).
+template <typename SI, typename SO, typename SF, typename A, bool BLOCKONLY, bool RESID, int RT, bool NTC, int G = 1>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<SI, A, RT>::value))) void k_dslash(const vec2_t<SI> *__restrict__ in, vec2_t<SO> *__restrict__ out,
                                                const vec2_t<SF> *__restrict__ links,
                                                const vec2_t<SF> *__restrict__ clov,
                                                const vec2_t<SO> *__restrict__ resid, DArgs a)
 {
-    int b, r0;
+    static_assert(G == 1 || (RT == 1 && !BLOCKONLY), "lanes share a site only with one right-hand side per lane");
+    int b, r0, s = threadIdx.x;
+    bool keep = true; // this lane's result is stored
     if (BLOCKONLY) {
         b = a.block_id;
         r0 = 0;
+    } else if (G > 1) {
+        constexpr int SPW = 64 / G; // sites per wavefront
+        const int wg = xcd_remap(blockIdx.x, gridDim.x);
+        const int bp = wg / a.ngroups; // block * G + part; the groups of a part are adjacent
+        b = bp / G;
+        const int l = threadIdx.x & 63;
+        s = (bp - b * G) * (4 * SPW) + (threadIdx.x >> 6) * SPW + l % SPW;
+        r0 = (wg - bp * a.ngroups) * G + l / SPW;
+        if (r0 >= a.nrhs) { // ragged last group: recompute the last right-hand side, store nothing
+            r0 = a.nrhs - 1;
+            keep = false;
+        }
+        if (a.active && !a.active[r0]) return; // per lane; the kernel has no barrier
     } else {
         const int wg = xcd_remap(blockIdx.x, gridDim.x);
         b = wg / a.ngroups;
         r0 = (wg - b * a.ngroups) * RT;
         if (RT == 1 && a.active && !a.active[r0]) return; // uniform over the workgroup
     }
-    const int nr = a.nrhs - r0 < RT ? a.nrhs - r0 : RT;
-    const int s = threadIdx.x;
+    const int nr = !keep ? 0 : (a.nrhs - r0 < RT ? a.nrhs - r0 : RT);
     int bc[4];
     block_coords(a.g, b, bc);
     cx<A> acc[RT][12];
@@ -235,8 +257,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         ro[rr] = (long)(r - r0) * 12 * BS + (a.in_off ? a.in_off[r] : 0);
         diag[rr] = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
     }
-    hops<BLOCKONLY, sizeof(A) == 8 && RT == 1, RT == 1 && sizeof(SI) <= 4, RT, SI, SF, A>(in, links, a, b, bc, r0, ro,
-                                                                                      s, acc);
+    hops<BLOCKONLY, (sizeof(A) == 8 || sizeof(SI) == 2) && RT == 1, RT == 1 && sizeof(SI) == 4, RT, SI, SF, A>(
+        in, links, a, b, bc, r0, ro, s, acc);
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
@@ -339,12 +361,16 @@ DArgs make_args(const dd_ctx *ctx, const double *m0, int nrhs)
 // must fit in registers next to the link
 // (FP64 arithmetic: one -- two already spill; FP32 arithmetic: up to three)
 template <typename SI, typename A> int pick_rt(int nrhs) { return sizeof(A) == 8 ? 1 : (nrhs >= 3 ? 3 : nrhs); }
+// lane-shared sites for several right-hand sides: FP64 input only (with FP32
+// input the variant spills and measured no faster; FP32 arithmetic keeps the
+// register forms, which measured faster than lane sharing)
+template <typename SI> constexpr bool LANE_SHARE = sizeof(SI) == 8;
 
-template <typename SI, typename SO, typename SF, typename A, bool RESID, int RT, bool NTC>
+template <typename SI, typename SO, typename SF, typename A, bool RESID, int RT, bool NTC, int G = 1>
 void launch_rt(dd_ctx *ctx, DArgs a, const void *in, void *out, int field_prec, const void *resid)
 {
-    a.ngroups = (a.nrhs + RT - 1) / RT;
-    k_dslash<SI, SO, SF, A, false, RESID, RT, NTC><<<ctx->g.nblocks * a.ngroups, BS, 0, ctx->stream>>>(
+    a.ngroups = (a.nrhs + RT * G - 1) / (RT * G);
+    k_dslash<SI, SO, SF, A, false, RESID, RT, NTC, G><<<ctx->g.nblocks * G * a.ngroups, BS, 0, ctx->stream>>>(
         static_cast<const vec2_t<SI> *>(in), static_cast<vec2_t<SO> *>(out),
         static_cast<const vec2_t<SF> *>(ctx->links[field_prec].p), static_cast<const vec2_t<SF> *>(ctx->clover[field_prec].p),
         static_cast<const vec2_t<SO> *>(resid), a);
@@ -377,6 +403,23 @@ Status launch(dd_ctx *ctx, const DArgs &a, const void *in, void *out, int field_
             // faster than the gather form there; FP16 storage and FP64
             // fields stay with the gather form)
             launch_lds<SI, SO, SF, A, Residency<true, true, 2>, RESID>(ctx, a, in, out, field_prec, resid);
+            DD_HIP_TRY(hipGetLastError());
+            return Status::ok();
+        }
+    }
+    if constexpr (LANE_SHARE<SI>) {
+        if (a.nrhs % 2 == 0) {
+            // an even number of right-hand sides: lanes share sites, G = 4
+            // when it divides the count, else 2 (a ragged lane group measured
+            // slower than G = 1); streaming clover loads when one group covers
+            // all right-hand sides
+            if (a.nrhs % 4 == 0) {
+                if (a.nrhs == 4) launch_rt<SI, SO, SF, A, RESID, 1, true, 4>(ctx, a, in, out, field_prec, resid);
+                else launch_rt<SI, SO, SF, A, RESID, 1, false, 4>(ctx, a, in, out, field_prec, resid);
+            } else {
+                if (a.nrhs == 2) launch_rt<SI, SO, SF, A, RESID, 1, true, 2>(ctx, a, in, out, field_prec, resid);
+                else launch_rt<SI, SO, SF, A, RESID, 1, false, 2>(ctx, a, in, out, field_prec, resid);
+            }
             DD_HIP_TRY(hipGetLastError());
             return Status::ok();
         }
