@@ -42,7 +42,7 @@ def test_apply_D_single(lat, prec):
     assert rel(out, ref) <= REL_TOL_APPLY[prec]
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 6, 12])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 8, 12])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_apply_D_multi_rhs_own_masses(lat, prec, n):
     """Full and partial lane groups of right-hand sides, each with its own mass."""
