@@ -41,7 +41,7 @@ WORKLOADS = {
     # name: dims, eps, m0, csw, smoother precision, nrhs, source
     "c2": dict(dims=(32, 32, 32, 64), eps=0.5, m0=-0.35, csw=1.0, sap="f32", nrhs=1, source="gaussian",
                text="32^3x64, random SU(3) eps=0.5, csw=1.0, m0=-0.35, 1 Gaussian RHS, SAP FP32 4^4 blocks "
-                    "nmr=4 ncy=4, FGMRES(20) FP64, tol 1e-10"),
+                    "nmr=4 ncy=12, FGMRES(20) FP64, tol 1e-10"),
     "c1": dict(dims=(8, 8, 8, 8), eps=0.3, m0=-0.2, csw=1.0, sap="f32", nrhs=1, source="gaussian",
                text="8^4, eps=0.3, csw=1.0, m0=-0.2, 1 Gaussian RHS, 4^4 blocks, FGMRES(20), tol 1e-10"),
     "c3": dict(dims=(48, 48, 48, 96), eps=0.6, m0=-0.38, csw=1.0, sap="f16", nrhs=1, source="gaussian",
@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=int, default=120)
     ap.add_argument("--no-standalone", action="store_true")
+    ap.add_argument("--ncy-scan", default="",
+                    help="comma-separated SAP cycle counts: time one mixed solve at each (e.g. 2,3,4,6)")
     return ap.parse_args()
 
 
@@ -272,15 +274,17 @@ def main():
     xd = torch.zeros_like(bd)
     m0 = np.full(nrhs, w["m0"])
 
-    def params(sap, eo=False):
+    def params(sap, eo=False, ncy=None):
         p = ddsap.default_params()
         p.sap_prec = ddsap.PREC[sap]
         p.sap_eo = int(eo)
+        if ncy is not None:
+            p.ncy = ncy
         return p
 
-    def one_solve(sap, eo=False):
+    def one_solve(sap, eo=False, ncy=None):
         xd.zero_()
-        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap, eo), raise_on_fail=False)
+        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap, eo, ncy), raise_on_fail=False)
         if st != ddsap.DD_OK:
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
@@ -345,6 +349,22 @@ def main():
                 "sweep_avg_ms": None if not sweep else round(sweep["total_ms"] / sweep["launches"], 4)}
             log(f"even-odd smoother {sap}: {info_eo[0]['iterations']} iterations, {t_eo * 1e3:.1f} ms")
         even_odd["mixed_speedup_over_plain"] = round(t_mixed / even_odd["mixed"]["time_s"], 3)
+
+    # sensitivity of the mixed solve to the SAP cycles per preconditioner call
+    # (the paper leaves the count open; 4 is the default)
+    ncy_scan = None
+    if args.ncy_scan:
+        ncy_scan = {}
+        for k in [int(v) for v in args.ncy_scan.split(",") if v.strip()]:
+            one_solve(w["sap"], ncy=k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info_k = one_solve(w["sap"], ncy=k)
+            torch.cuda.synchronize()
+            t_k = time.perf_counter() - t0
+            ncy_scan[str(k)] = {"time_s": round(t_k, 4), "iterations": info_k[0]["iterations"],
+                                "rel_residual": max(i["rel_residual"] for i in info_k)}
+            log(f"ncy={k}: {info_k[0]['iterations']} iterations, {t_k * 1e3:.1f} ms")
 
     # multi-RHS: the same right-hand sides solved one at a time, for the fusion gain
     sequential = None
@@ -439,6 +459,7 @@ def main():
         "iterations": {"mixed": infos[-1][0]["iterations"],
                        "fp64": None if info64 is None else info64[0]["iterations"]},
         "even_odd": even_odd,
+        **({"ncy_sensitivity": ncy_scan} if ncy_scan else {}),
         "final_rel_residual": max(i["rel_residual"] for i in infos[-1]),
         "kernels": breakdown,
         "cpu_baseline": cpu,

@@ -87,7 +87,7 @@ typedef struct {
     int m;            /* Krylov dimension per restart cycle, 1..32 (20)         */
     double tol;       /* stop when ||b - D x||_2 / ||b||_2 <= tol (1e-10)       */
     int max_restarts; /* restart cycles before DD_NOT_CONVERGED (100)            */
-    int ncy;          /* SAP cycles per preconditioner call; 0 = no precond (4) */
+    int ncy;          /* SAP cycles per preconditioner call; 0 = no precond (12)*/
     int nmr;          /* MR steps per block and sweep (4)                        */
     int sap_prec;     /* dd_prec of the smoother (DD_F32)                        */
     int sap_eo;       /* 1: even-odd preconditioned block solves (dd_sap_eo), 0 */
@@ -222,7 +222,7 @@ typedef struct {
     int m;                   /* FGMRES(m), 1..32 (20)                                 */
     double tol;              /* per right-hand side (1e-10)                          */
     int max_restarts;        /* (100)                                                 */
-    int ncy, nmr;            /* SAP cycles and MR steps (4, 4)                        */
+    int ncy, nmr;            /* SAP cycles and MR steps (12, 4)                       */
     int sap_prec;            /* smoother precision (DD_F32)                           */
     int use_graphs;          /* replay captured hipGraphs for the Arnoldi step (1)    */
     int sap_eo;              /* even-odd preconditioned block solves (0)              */

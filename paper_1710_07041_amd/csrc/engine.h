@@ -15,7 +15,7 @@ constexpr int ENGINE_MAXM = 32; // largest Krylov dimension
 struct EngineParams {
     int width = 1;
     int m = 20;
-    int ncy = 4;
+    int ncy = 12;
     int nmr = 4;
     int sap_prec = DD_F32;
     bool sap_eo = false; // even-odd preconditioned block solves

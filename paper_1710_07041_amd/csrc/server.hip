@@ -230,7 +230,7 @@ void dd_server_default_config(dd_server_config *c)
     c->m = 20;
     c->tol = 1e-10;
     c->max_restarts = 100;
-    c->ncy = 4;
+    c->ncy = 12;
     c->nmr = 4;
     c->sap_prec = DD_F32;
     c->sap_eo = 0;
