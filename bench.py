@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=int, default=120)
     ap.add_argument("--no-standalone", action="store_true")
+    ap.add_argument("--sap-half-fields", action="store_true",
+                    help="the FP32 smoother reads FP16 links and clover (dd_set_sap_half_fields)")
     ap.add_argument("--ncy-scan", default="",
                     help="comma-separated SAP cycle counts: time one mixed solve at each (e.g. 2,3,4,6)")
     return ap.parse_args()
@@ -269,6 +271,8 @@ def main():
     ctx = ddsap.Context(dims, (1, 1, 1, -1))
     ctx.set_gauge(U, w["csw"])
     compressed = ctx.link_compression  # SU(3) links: two rows stored per link are read
+    if args.sap_half_fields:
+        ctx.set_sap_half_fields(True)
     del U
     bd = torch.from_numpy(np.ascontiguousarray(b)).to("cuda")
     xd = torch.zeros_like(bd)
@@ -441,7 +445,8 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": w["text"], "lattice": "x".join(map(str, dims)), "nrhs": nrhs,
-                   "smoother": w["sap"], "parallelism": "single GPU", "link_compression": compressed},
+                   "smoother": w["sap"], "parallelism": "single GPU", "link_compression": compressed,
+                   **({"sap_half_fields": True} if args.sap_half_fields else {})},
         "roofline": roof,
         "roofline_dslash": {"bound": "hbm", "kernel": main_cls, "achieved": rd["gbs"], "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": rd["frac_hbm"], "traffic": traffic.get(main_cls),

@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define DD_ABI_VERSION 3
+#define DD_ABI_VERSION 4
 #define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
 
 typedef enum {
@@ -145,6 +145,23 @@ dd_status dd_set_link_compression(dd_ctx *ctx, int enable);
 
 /* 1 if gauge compression is on, 0 if off, -1 for a NULL context. */
 int dd_link_compression(const dd_ctx *ctx);
+
+/* Half-precision fields under the FP32 smoother (Sec. 3.1: some data
+ * structures stored as 16-bit floats within mixed precision).  With
+ * enable = 1 the plain FP32 Schwarz sweep -- dd_sap with DD_F32, and dd_solve
+ * or a server with an FP32 smoother and sap_eo = 0 -- reads the FP16 copies of
+ * the links and the clover term that dd_set_gauge / dd_set_clover store;
+ * spinors, the MR arithmetic and the FP64 outer iteration keep their
+ * precisions.  The block solves then use D_BB with FP16-rounded entries
+ * (relative rounding 2^-11), which the flexible outer iteration absorbs; the
+ * solve still stops on the FP64 true residual.  enable = 0 (the default)
+ * reads FP32 fields.  Other smoother precisions and the even-odd sweep are
+ * unaffected.  Applies to calls made afterwards.  DD_INVALID_ARG for a NULL
+ * context. */
+dd_status dd_set_sap_half_fields(dd_ctx *ctx, int enable);
+
+/* 1 if the FP32 smoother reads FP16 fields, 0 if not, -1 for a NULL context. */
+int dd_sap_half_fields(const dd_ctx *ctx);
 
 /* Replace the clover term by an explicit one (host pointer, canonical clover
  * layout, 144*V doubles; each 6x6 half must be Hermitian, only its upper

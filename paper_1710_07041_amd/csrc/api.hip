@@ -205,6 +205,15 @@ dd_status dd_set_link_compression(dd_ctx *ctx, int enable)
 
 int dd_link_compression(const dd_ctx *ctx) { return ctx ? (ctx->link_r12 ? 1 : 0) : -1; }
 
+dd_status dd_set_sap_half_fields(dd_ctx *ctx, int enable)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    ctx->sap_half_fields = enable != 0;
+    return DD_OK;
+}
+
+int dd_sap_half_fields(const dd_ctx *ctx) { return ctx ? (ctx->sap_half_fields ? 1 : 0) : -1; }
+
 dd_status dd_set_clover(dd_ctx *ctx, const double *C_host)
 {
     if (!ctx) return DD_INVALID_ARG;

@@ -972,7 +972,7 @@ Status Engine::launch_step()
     const bool use_graph = e.P.graphs && !e.ctx->prof.on;
     if (use_graph) {
         // the kernels' arguments also depend on the link format
-        const int key = (bucket * 4 + e.sap_prec) * 2 + (e.ctx->link_r12 ? 1 : 0);
+        const int key = ((bucket * 4 + e.sap_prec) * 2 + (e.ctx->link_r12 ? 1 : 0)) * 2 + (e.ctx->sap_half_fields ? 1 : 0);
         auto it = e.graphs.find(key);
         if (it == e.graphs.end()) {
             hipGraph_t g = nullptr;

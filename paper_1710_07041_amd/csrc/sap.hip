@@ -109,10 +109,12 @@ template <typename A, typename RES> struct DelStore {
 // Whether the plain sweep of storage type S carries the block residual.
 template <typename S> constexpr bool SAP_CARRY = !std::is_same<S, double>::value;
 
-template <typename S, typename A, typename RES>
+// SF is the storage type of the links and the clover term (S, or FP16 fields
+// under FP32 spinors).
+template <typename S, typename A, typename RES, typename SF = S>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))) void k_sap_sweep(
-    const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<S> *__restrict__ links,
-    const vec2_t<S> *__restrict__ clov, vec2_t<S> *__restrict__ faces, vec2_t<S> *__restrict__ resid, SArgs a)
+    const vec2_t<S> *__restrict__ eta0, vec2_t<S> *__restrict__ psi0, const vec2_t<SF> *__restrict__ links,
+    const vec2_t<SF> *__restrict__ clov, vec2_t<S> *__restrict__ faces, vec2_t<S> *__restrict__ resid, SArgs a)
 {
     constexpr bool REGLINKS = RES::links;
     static_assert(REGLINKS, "the face buffers assume register-resident links");
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     load_links4<A, true>(links + (long)b * 4 * 9 * BS + s, a.r12, (A)(-0.5), U);
     cx<A> cl[RES::ncl];
     if (RES::clover || RES::clover_half) {
-        const vec2_t<S> *cp = clov + (long)b * 36 * BS + s;
+        const vec2_t<SF> *cp = clov + (long)b * 36 * BS + s;
 #pragma unroll
         for (int e = 0; e < RES::ncl; ++e) cl[e] = ldc_stream<A>(cp + e * BS);
     }
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 #pragma unroll
             for (int c = 0; c < 12; ++c) d0[c] = a.mode == 2 ? ldc<A>(psi + sp + c * BS) : mk<A>(0, 0);
             if (a.mode == 2) {
-                block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, d0, q);
+                block_apply<SF, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, d0, q);
             } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(&er[c]) - q[c];
         // MR on D_BB: delta += alpha r, r -= alpha q
         for (int it = 0; it < a.nmr; ++it) {
-            block_apply<S, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
+            block_apply<SF, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
             cx<A> alpha;
             if (!mr_alpha(L, lane, wave, q, rr, alpha)) break;
 #pragma unroll
@@ -593,7 +595,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     }
 }
 
-template <typename S, typename A, typename RES, bool EO>
+template <typename S, typename A, typename RES, bool EO, typename SF = S>
 Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces, void *resid)
 {
     // algorithmic traffic of one colour sweep: links + clover once, eta (or
@@ -601,9 +603,10 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
     // in the plain form, the residual carried to the next visit
     const double sites = 256.0 * a.nblk, sb = (double)sizeof(S), n = a.nrhs;
     constexpr bool CARRY = !EO && SAP_CARRY<S>;
+    const int fprec = sizeof(SF) == 8 ? DD_F64 : (sizeof(SF) == 4 ? DD_F32 : DD_F16);
     // (links count 72 reals per site also when compressed: the method's volume)
-    const double by = sites * (144.0 * sb + n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0) +
-                                                      (CARRY && a.write_r ? 24.0 : 0.0)));
+    const double by = sites * (144.0 * (double)sizeof(SF) +
+                               n * sb * (24.0 + 24.0 + (a.mode == 2 ? 24.0 : 0.0) + (CARRY && a.write_r ? 24.0 : 0.0)));
     // recomputing the block residual costs one operator application when
     // psi_B != 0; carrying it costs none.  The even-odd form adds one
     // in-block hop application (the right-hand side and the odd
@@ -618,9 +621,9 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
             static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
             static_cast<vec2_t<S> *>(faces), a);
     else
-        k_sap_sweep<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
+        k_sap_sweep<S, A, RES, SF><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
-            static_cast<const vec2_t<S> *>(ctx->links[prec].p), static_cast<const vec2_t<S> *>(ctx->clover[prec].p),
+            static_cast<const vec2_t<SF> *>(ctx->links[fprec].p), static_cast<const vec2_t<SF> *>(ctx->clover[fprec].p),
             static_cast<vec2_t<S> *>(faces), static_cast<vec2_t<S> *>(resid), a);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
@@ -658,6 +661,11 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
 {
     if (!eta || !psi || !ctx->links[prec].p || !ctx->clover[prec].p || (!m0 && !(slots && slots->m0_dev)))
         return Status{DD_INVALID_ARG, "SAP: missing buffer"};
+    // FP16 links and clover under the plain FP32 sweep (the even-odd sweep
+    // keeps its own precision's fields)
+    const bool half_fields = prec == DD_F32 && !eo && ctx->sap_half_fields;
+    if (half_fields && (!ctx->links[DD_F16].p || !ctx->clover[DD_F16].p))
+        return Status{DD_INVALID_ARG, "SAP: missing FP16 fields"};
     if (ncy == 0) {
         if (slots) return Status{DD_INVALID_ARG, "SAP: zero cycles with per-slot offsets"};
         DD_HIP_TRY(hipMemsetAsync(psi, 0, spinor_bytes(ctx->g, prec, nrhs), ctx->stream));
@@ -703,6 +711,8 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
                 else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
             } else {
                 if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces, resid)));
+                else if (prec == DD_F32 && half_fields)
+                    DD_TRY((sweep<float, float, ResF32, false, __half>(ctx, a, prec, eta, psi, faces, resid)));
                 else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces, resid)));
                 else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces, resid)));
             }

@@ -37,7 +37,7 @@ DD_MAX_RHS = 16
 
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
-    "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
+    "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_sap_half_fields", "dd_sap_half_fields", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
     "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_profile_enable", "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
@@ -88,6 +88,8 @@ _sigs = {
     "dd_set_clover": ([_vp, _vp], _i),
     "dd_set_link_compression": ([_vp, _i], _i),
     "dd_link_compression": ([_vp], _i),
+    "dd_set_sap_half_fields": ([_vp, _i], _i),
+    "dd_sap_half_fields": ([_vp], _i),
     "dd_spinor_bytes": ([_vp, _i, _i], _sz),
     "dd_pack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
     "dd_unpack_spinor": ([_vp, _vp, _vp, _i, _i], _i),
@@ -194,6 +196,15 @@ class Context:
     @property
     def link_compression(self) -> bool:
         return _lib.dd_link_compression(self._h) == 1
+
+    def set_sap_half_fields(self, enable):
+        """dd_set_sap_half_fields: the plain FP32 smoother reads FP16 links
+        and clover."""
+        self._check(_lib.dd_set_sap_half_fields(self._h, 1 if enable else 0))
+
+    @property
+    def sap_half_fields(self) -> bool:
+        return _lib.dd_sap_half_fields(self._h) == 1
 
     def set_clover(self, C):
         """C: host complex128 array (V, 2, 6, 6): the two chiral 6x6 halves."""

@@ -69,6 +69,44 @@ def test_sap_multi_rhs(lat, prec):
         assert np.array_equal(out[r], gpu_sap(lat, eta[r], m0[r], 2, 4, prec))
 
 
+def round_fp16(z):
+    """Each real part rounded as the library stores FP16 fields: to FP32, then
+    to FP16, both to nearest even."""
+    f = lambda a: a.astype(np.float32).astype(np.float16).astype(np.float64)
+    return f(z.real) + 1j * f(z.imag)
+
+
+@pytest.mark.parametrize("ncy,nmr", [(1, 4), (4, 4)])
+def test_sap_half_fields_is_sap_on_rounded_fields(lat, ncy, nmr):
+    """FP16 links and clover under the FP32 smoother.  With all nine link
+    entries read, the result is the oracle's SAP on the FP16-rounded fields
+    to 2e-5, while the rounding itself moves SAP by about 1e-4; with gauge
+    compression the third row is rebuilt from the rounded rows, and the
+    result stays within 1e-3 of the exact SAP.  A batch of right-hand sides
+    gives each one's result bitwise."""
+    eta = synth.gaussian_spinor(lat.dims, seed=3)
+    m0 = -0.2
+    ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0, eta, ncy, nmr, BC)
+    ref16 = oracle.sap(lat.dims, (4, 4, 4, 4), round_fp16(lat.U), round_fp16(lat.C), m0, eta, ncy, nmr, BC)
+    assert rel(ref16, ref) >= 5e-5  # the pin below tells FP16 fields from FP32 ones
+    try:
+        lat.ctx.set_sap_half_fields(True)
+        assert lat.ctx.sap_half_fields
+        lat.ctx.set_link_compression(False)
+        assert rel(gpu_sap(lat, eta, m0, ncy, nmr, "f32"), ref16) <= 2e-5
+        lat.ctx.set_link_compression(True)
+        assert rel(gpu_sap(lat, eta, m0, ncy, nmr, "f32"), ref) <= 1e-3
+        etas = synth.gaussian_spinor(lat.dims, nrhs=2, seed=6)
+        m0s = np.array([-0.3, 0.1])
+        batch = gpu_sap(lat, etas, m0s, ncy, nmr, "f32", nrhs=2)
+        for r in range(2):
+            assert np.array_equal(batch[r], gpu_sap(lat, etas[r], m0s[r], ncy, nmr, "f32"))
+    finally:
+        lat.ctx.set_sap_half_fields(False)
+        lat.ctx.set_link_compression(True)
+    assert rel(gpu_sap(lat, eta, m0, ncy, nmr, "f32"), ref) <= REL_TOL_SAP["f32"]
+
+
 def gpu_solve(lat, b, m0, sap_prec, nrhs=None, **kw):
     from paper_1710_07041_amd import ddsap
     import torch
@@ -98,6 +136,21 @@ def test_solve_c1_residual_against_oracle(c1, sap_prec):
     r = b - oracle.apply_D(c1.dims, c1.U, c1.C, m0, x, BC)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
     assert info[0]["rel_residual"] <= 1e-10
+
+
+def test_solve_half_fields_residual_against_oracle(c1):
+    """FP16 fields under the FP32 smoother change the preconditioner only:
+    the solve still reaches the FP64 true residual, checked by the oracle."""
+    b = synth.gaussian_spinor(c1.dims, seed=0)
+    m0 = -0.2
+    c1.ctx.set_sap_half_fields(True)
+    try:
+        st, info, x = gpu_solve(c1, b, m0, "f32")
+    finally:
+        c1.ctx.set_sap_half_fields(False)
+    assert st == 0 and info[0]["status"] == 0
+    r = b - oracle.apply_D(c1.dims, c1.U, c1.C, m0, x, BC)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
 
 
 def test_solve_mixed_vs_fp64_agree(c1):
