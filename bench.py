@@ -169,7 +169,8 @@ def serve_main(args):
     gen = torch.Generator(device="cuda")
 
     def make_server(prec):
-        srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb << 30, max_width=12, use_graphs=1, sap_prec=prec)
+        srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb << 30, max_width=12, use_graphs=1, sap_prec=prec,
+                           sap_half_fields=1 if args.sap_half_fields and prec == "f32" else 0)
         fids = [srv.add_field(dims, U, 1.0) for dims, U in fields]
         return srv, fids, [srv.field_info(f)[0] for f in fids]
 
@@ -237,7 +238,8 @@ def serve_main(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "serving: resident 16^4, 24^3x48, 32^3x64 (eps=0.5, csw=1), m0~U[-0.38,-0.2], "
                                "1-12 Gaussian RHS per request, SAP FP32 + FGMRES(20) FP64 to 1e-10, "
-                               f"HBM budget {args.serve_budget_gb} GiB", "slots_per_field": widths},
+                               f"HBM budget {args.serve_budget_gb} GiB", "slots_per_field": widths,
+                   **({"sap_half_fields": True} if args.sap_half_fields else {})},
         "serving": {"saturation": sat, "poisson_0.7x": pois, "server_stats": st,
                     "fp64_smoother": {"slots_per_field": widths64, "saturation": sat64,
                                       "mixed_over_fp64_rhs_per_s": round(sat["rhs_per_s"] / sat64["rhs_per_s"], 3)}},

@@ -243,6 +243,8 @@ typedef struct {
     int sap_prec;            /* smoother precision (DD_F32)                           */
     int use_graphs;          /* replay captured hipGraphs for the Arnoldi step (1)    */
     int sap_eo;              /* even-odd preconditioned block solves (0)              */
+    int sap_half_fields;     /* FP32 smoother reads FP16 links and clover (0); see
+                                dd_set_sap_half_fields                                */
 } dd_server_config;
 
 typedef struct {

@@ -235,6 +235,7 @@ void dd_server_default_config(dd_server_config *c)
     c->sap_prec = DD_F32;
     c->sap_eo = 0;
     c->use_graphs = 1;
+    c->sap_half_fields = 0;
 }
 
 dd_status dd_server_create(const dd_server_config *cfg, dd_server **out)
@@ -284,6 +285,7 @@ dd_status dd_server_add_field(dd_server *s, const int dims[4], const int bcs[4],
         return st;
     }
     st = dd_set_gauge(f.ctx, U_host, csw);
+    if (st == DD_OK) st = dd_set_sap_half_fields(f.ctx, s->cfg.sap_half_fields);
     if (st != DD_OK) {
         s->err = std::string("server: ") + dd_last_error(f.ctx);
         dd_destroy(f.ctx);

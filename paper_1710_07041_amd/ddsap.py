@@ -64,7 +64,7 @@ class dd_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_width", ctypes.c_int), ("m", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int), ("ncy", ctypes.c_int),
                 ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("sap_eo", ctypes.c_int)]
+                ("sap_eo", ctypes.c_int), ("sap_half_fields", ctypes.c_int)]
 
 
 class dd_server_stats(ctypes.Structure):

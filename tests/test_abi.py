@@ -48,4 +48,4 @@ def test_abi_version_and_defaults(lib):
     p = ddsap.default_params()
     assert (p.m, p.tol, p.max_restarts, p.ncy, p.nmr, p.sap_prec, p.sap_eo) == (20, 1e-10, 100, 12, 4, ddsap.DD_F32, 0)
     c = ddsap.default_server_config()
-    assert (c.sap_prec, c.use_graphs, c.sap_eo, c.ncy, c.nmr) == (ddsap.DD_F32, 1, 0, 12, 4)
+    assert (c.sap_prec, c.use_graphs, c.sap_eo, c.ncy, c.nmr, c.sap_half_fields) == (ddsap.DD_F32, 1, 0, 12, 4, 0)

@@ -25,11 +25,12 @@ def fields():
     return out
 
 
-def solo(dims, U, m0, b, sap="f32", eo=0):
+def solo(dims, U, m0, b, sap="f32", eo=0, half=0):
     import torch
     from paper_1710_07041_amd import ddsap
     ctx = ddsap.Context(dims, BC)
     ctx.set_gauge(U, 1.0)
+    ctx.set_sap_half_fields(bool(half))
     bd = to_dev(b)
     xd = torch.zeros_like(bd)
     p = ddsap.default_params()
@@ -53,11 +54,12 @@ def make_requests(fields, n, seed=0):
     return reqs
 
 
-@pytest.mark.parametrize("graphs,eo", [(1, 0), (0, 0), (1, 1)], ids=["graphs", "nographs", "graphs-evenodd"])
-def test_serve_mix_equals_alone(fields, graphs, eo):
+@pytest.mark.parametrize("graphs,eo,half", [(1, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1)],
+                         ids=["graphs", "nographs", "graphs-evenodd", "graphs-halffields"])
+def test_serve_mix_equals_alone(fields, graphs, eo, half):
     import torch
     from paper_1710_07041_amd import ddsap
-    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30, sap_eo=eo)
+    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30, sap_eo=eo, sap_half_fields=half)
     fids = [srv.add_field(dims, U, 1.0, BC) for dims, U, _ in fields]
     for f in fids:
         assert srv.field_info(f)[0] == 3
@@ -85,7 +87,7 @@ def test_serve_mix_equals_alone(fields, graphs, eo):
         for r in range(b.shape[0]):
             res = b[r] - oracle.apply_D(dims, U, C, m0[r], x[r], BC)
             assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10
-        xs = solo(dims, U, m0, b, eo=eo)
+        xs = solo(dims, U, m0, b, eo=eo, half=half)
         assert rel(x, xs) <= 1e-8
 
 
