@@ -146,8 +146,8 @@ dd_status dd_set_link_compression(dd_ctx *ctx, int enable);
 /* 1 if gauge compression is on, 0 if off, -1 for a NULL context. */
 int dd_link_compression(const dd_ctx *ctx);
 
-/* Half-precision fields under the FP32 smoother (Sec. 3.1: some data
- * structures stored as 16-bit floats within mixed precision).  With
+/* Half-precision fields under the FP32 smoother (Sec. 3.1 keeps part of its
+ * data in 16-bit floating point as a further mixed-precision step).  With
  * enable = 1 the plain FP32 Schwarz sweep -- dd_sap with DD_F32, and dd_solve
  * or a server with an FP32 smoother and sap_eo = 0 -- reads the FP16 copies of
  * the links and the clover term that dd_set_gauge / dd_set_clover store;
