@@ -3,8 +3,8 @@
 // Flexible GMRES (Saad, SIAM J. Sci. Comput. 14 (1993) 461) with an FP64
 // outer iteration and the red-black Schwarz smoother in FP64, FP32 or FP16
 // storage -- the mixed-precision structure of the paper's solver (Sec. 3.1:
-// mixed precision, some data structures in half precision; the Schwarz method
-// as the fine-grid smoother).  Flexible GMRES is needed because SAP with MR
+// a low-precision smoother with part of its data in 16-bit floating point,
+// and the Schwarz method as the fine-grid smoother).  Flexible GMRES is needed because SAP with MR
 // block solves is not a linear map of its input.
 //
 // One engine serves `width` right-hand-side slots of one lattice.  Every slot
