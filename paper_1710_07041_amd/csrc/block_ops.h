@@ -122,6 +122,38 @@ template <typename A> __device__ __forceinline__ cx<A> lane_fetch(const cx<A> &v
     }
 }
 
+// The x and y neighbours of a 4^4 block (site s = x + 4y + 16z + 64t on
+// thread s) are lanes of the same quad (x) or 16-lane row (y): DPP moves
+// reach them at VALU rate, rotating within the quad (x +- 1 mod 4) or the row
+// (y +- 1 mod 4, i.e. lane +- 4 mod 16).  Lanes whose neighbour lies outside
+// the block get their own block's wrapped site and never use it.  z crosses
+// rows and keeps ds_bpermute.
+template <int CTRL> __device__ __forceinline__ int dpp_mov(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int MU, int DIR, typename A> __device__ __forceinline__ cx<A> lane_hop(const cx<A> &v, int sn)
+{
+    if constexpr (MU >= 2) {
+        return lane_fetch<A>(v, (sn & 63) << 2);
+    } else {
+        // quad_perm [1,2,3,0] / [3,0,1,2]: lane k reads lane k + 1 / k - 1 of
+        // its quad; row_ror:12 / row_ror:4: lane i reads lane i + 4 / i - 4
+        // of its row of 16
+        constexpr int CTRL = MU == 0 ? (DIR > 0 ? 0x39 : 0x93) : (DIR > 0 ? 0x12C : 0x124);
+        if constexpr (sizeof(A) == 4) {
+            return mk<A>(__int_as_float(dpp_mov<CTRL>(__float_as_int(v.re))),
+                         __int_as_float(dpp_mov<CTRL>(__float_as_int(v.im))));
+        } else {
+            const long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
+            const int r0 = dpp_mov<CTRL>((int)r), r1 = dpp_mov<CTRL>((int)(r >> 32));
+            const int i0 = dpp_mov<CTRL>((int)i), i1 = dpp_mov<CTRL>((int)(i >> 32));
+            return mk<A>(__longlong_as_double(((long long)r1 << 32) | (unsigned)r0),
+                         __longlong_as_double(((long long)i1 << 32) | (unsigned)i0));
+        }
+    }
+}
+
 // One direction of the in-block exchange with the link given in registers,
 // already multiplied by the hop factor -1/2.  With LANES (site s = x + 4y +
 // 16z + 64t of the 4^4 block is thread s) a wavefront holds one t-slice: the
@@ -145,7 +177,7 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
         // +mu hop: the neighbour's projected half spinor, times this site's link
         proj_minus<MU>(v, h);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = lane_fetch<A>(h[c], (snf & 63) << 2);
+        for (int c = 0; c < 6; ++c) t[c] = lane_hop<MU, +1, A>(h[c], snf);
         if (inf) {
             su3_mul(U, t, h);
             if (wraps) recon_minus<MU>(q, h, (A)sign_f);
@@ -155,7 +187,7 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
         proj_plus<MU>(v, h);
         su3_mul_adj(U, h, t);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) h[c] = lane_fetch<A>(t[c], (snb & 63) << 2);
+        for (int c = 0; c < 6; ++c) h[c] = lane_hop<MU, -1, A>(t[c], snb);
         if (inbk) {
             if (wraps) recon_plus<MU>(q, h, (A)sign_b);
             else recon_plus1<MU>(q, h);
