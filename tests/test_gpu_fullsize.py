@@ -102,6 +102,24 @@ def test_c2_mixed_solve_eo_oracle_residual(c2, c2_clover):
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
 
 
+def test_c2_mixed_solve_half_fields_oracle_residual(c2, c2_clover):
+    """The same solve with FP16 links and clover under the FP32 smoother."""
+    import torch
+    from paper_1710_07041_amd import ddsap
+    b = synth.gaussian_spinor(c2.dims, seed=0)
+    bd = to_dev(b)[None]
+    xd = torch.zeros_like(bd)
+    c2.ctx.set_sap_half_fields(True)
+    try:
+        st, info = c2.ctx.solve(-0.35, bd, xd, 1, ddsap.default_params())
+    finally:
+        c2.ctx.set_sap_half_fields(False)
+    assert st == ddsap.DD_OK
+    x = to_host(xd)[0]
+    r = b - oracle.apply_D(c2.dims, c2.U, c2_clover, -0.35, x, BC)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
 def test_c4_point_sources_oracle_residual(c2, c2_clover):
     """Twelve spin-colour point sources solved fused; each residual <= 1e-10 by the oracle."""
     import torch
