@@ -17,9 +17,13 @@ namespace dd {
 // Two buffers, used by alternate directions: direction mu + 2 overwrites the
 // buffer of direction mu only after every thread has passed the barrier of
 // direction mu + 1, i.e. after all reads of direction mu; so each direction
-// needs one barrier, not two.  When the x, y and z hops go across lanes
-// (exchange_dir with LANES) only buffer 1 (t) is used, and the plain Schwarz
-// sweep keeps each site's psi_B in buffer 0 meanwhile.
+// needs one barrier, not two, as long as all four directions go through LDS.
+// When the x, y and z hops go across lanes (exchange_dir with LANES) only
+// buffer 1 (t) is used, with one barrier per application: two applications
+// in a row then need a barrier between them (the caller's), or a slow
+// wavefront could still be reading the first one's t hops while a fast one
+// writes the second's.  The plain Schwarz sweep keeps each site's psi_B in
+// buffer 0 meanwhile.
 template <typename A> struct Lds {
     cx<A> hf[2][6][BS]; // projected half spinors for +mu hops
     cx<A> hb[2][6][BS]; // U^+ times projected half spinors for -mu hops

@@ -142,6 +142,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
     }
 
     for (int r = 0; r < a.nrhs; ++r) {
+        // with nmr = 0 the previous right-hand side's last t-hop reads are
+        // not yet fenced by an MR barrier
+        __syncthreads();
         if (a.active && !a.active[r]) continue; // uniform over the workgroup
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
         const vec2_t<S> *__restrict__ eta = eta0 + (a.eta_off ? a.eta_off[r] : 0);
@@ -191,6 +194,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         if (a.mode != 0) face_consume<S, A>(a.g, b, bc, s, r, a.nrhs, faces, U, q);
 #pragma unroll
         for (int c = 0; c < 12; ++c) rr[c] = ldc<A>(&er[c]) - q[c];
+        // the recomputed residual's t-hop reads end before the first MR
+        // application rewrites that LDS buffer
+        if (!CARRY && a.mode == 2) __syncthreads();
         // MR on D_BB: delta += alpha r, r -= alpha q
         for (int it = 0; it < a.nmr; ++it) {
             block_apply<SF, A, RES>(L, a.g, b, bc, s, U, cl, links, clov, diag, rr, q);
