@@ -63,6 +63,7 @@ def lib():
         L.or_clover_site.argtypes = [ip, vp, d, l_, vp]
         L.or_apply_D.argtypes = [ip, ip, vp, vp, d, vp, vp]
         L.or_apply_D_sites.argtypes = [ip, ip, vp, d, d, vp, vp, l_, vp]
+        L.or_apply_D_sites_nv.argtypes = [ip, ip, vp, d, d, vp, l_, vp, l_, vp]
         L.or_apply_DBB.argtypes = [ip, ip, ip, vp, vp, d, l_, vp, vp]
         L.or_apply_DBB.restype = i_
         L.or_mr_block.argtypes = [ip, ip, ip, vp, vp, d, l_, i_, vp, vp, vp]
@@ -138,6 +139,36 @@ def apply_D_sites(dims, U, csw, m0, psi, sites, bc=DEFAULT_BC):
     lib().or_apply_D_sites(_ivec(dims), _ivec(bc), _p(U), float(csw), float(m0), _p(psi), _p(sites),
                            len(sites), _p(out))
     return out
+
+
+def apply_D_sites_multi(dims, U, csw, m0, psis, sites, bc=DEFAULT_BC):
+    """(D psi_v)(x) for several vectors psis (n, V, 4, 3) at the listed sites;
+    returns (n, len(sites), 4, 3).  The clover term is formed once per site."""
+    V = int(np.prod(dims))
+    U = _c(U, (V, 4, 3, 3))
+    psis = np.ascontiguousarray(psis, dtype=np.complex128)
+    nvec = psis.size // (V * 12)
+    psis = psis.reshape(nvec, V, 4, 3)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((nvec, len(sites), 4, 3), dtype=np.complex128)
+    lib().or_apply_D_sites_nv(_ivec(dims), _ivec(bc), _p(U), float(csw), float(m0), _p(psis), nvec, _p(sites),
+                              len(sites), _p(out))
+    return out
+
+
+def rel_residuals(dims, U, csw, m0, b, xs, bc=DEFAULT_BC, chunk=1 << 20):
+    """||b - D x|| / ||b|| for each x in xs (n, V, 4, 3), evaluated over the
+    whole lattice in chunks of sites with the clover term formed on the fly
+    (no field-sized clover array)."""
+    V = int(np.prod(dims))
+    b = _c(b, (V, 4, 3))
+    xs = np.ascontiguousarray(xs, dtype=np.complex128).reshape(-1, V, 4, 3)
+    acc = np.zeros(xs.shape[0])
+    for start in range(0, V, chunk):
+        sites = np.arange(start, min(V, start + chunk), dtype=np.int64)
+        dx = apply_D_sites_multi(dims, U, csw, m0, xs, sites, bc)
+        acc += np.sum(np.abs(b[sites][None] - dx) ** 2, axis=(1, 2, 3))
+    return np.sqrt(acc) / np.linalg.norm(b)
 
 
 def apply_DBB(dims, block, U, C, m0, block_id, psi, bc=DEFAULT_BC):

@@ -273,6 +273,19 @@ void or_apply_D_sites(const int L[4], const int bcs[4], const double complex *U,
     }
 }
 
+void or_apply_D_sites_nv(const int L[4], const int bcs[4], const double complex *U, double csw, double m0,
+                         const double complex *in, long nvec, const long *sites, long n, double complex *out)
+{
+    long V = volume_of(L);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        double complex Cx[144];
+        or_clover_site(L, U, csw, sites[k], Cx);
+        for (long v = 0; v < nvec; ++v)
+            dirac_site(L, bcs, U, Cx, m0, in + v * V * 12, sites[k], NULL, out + (v * n + k) * 12);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Blocks                                                                    */
 /* ------------------------------------------------------------------------ */

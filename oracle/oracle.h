@@ -67,6 +67,12 @@ void or_apply_D_sites(const int L[4], const int bcs[4], const double complex *U,
                       double m0, const double complex *in, const long *sites, long n,
                       double complex *out);
 
+/* The same for nvec vectors in[nvec][V][12] at once (the clover term of a
+ * site is formed once for all of them); out[nvec][n][12]. */
+void or_apply_D_sites_nv(const int L[4], const int bcs[4], const double complex *U, double csw,
+                         double m0, const double complex *in, long nvec, const long *sites, long n,
+                         double complex *out);
+
 /* out_B = D_BB in_B for block `block_id`: every hop whose neighbour lies
  * outside the block is dropped.  in/out are whole-lattice canonical arrays;
  * only the sites of the block are read and written.  Returns 0, or -1 if the

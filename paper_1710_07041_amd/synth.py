@@ -14,12 +14,15 @@ Canonical host layouts (complex128 numpy arrays):
 
 Gauge links follow the recipe of the synthetic workloads: ``U = exp(i eps H)``
 with ``H = sum_a h_a lambda_a / 2``, ``h_a ~ N(0, 1)`` i.i.d. over the eight
-Gell-Mann matrices, exponentiated through the Hermitian eigendecomposition in
-float64.  Draw order: for every site (lexicographic), for every direction, the
+Gell-Mann matrices, exponentiated in float64 by the Cayley-Hamilton closed
+form (the Hermitian eigendecomposition for the rare near-degenerate
+spectra).  Draw order: for every site (lexicographic), for every direction, the
 eight ``h_a``; right-hand sides are drawn afterwards from their own generator
 stream (real part, then imaginary part, each ``N(0, 1)``).
 """
 from __future__ import annotations
+
+import os
 
 import numpy as np
 
@@ -63,12 +66,14 @@ def _exp_i_hermitian_eigh(H: np.ndarray, eps: float) -> np.ndarray:
     return (W * phase[..., None, :]) @ np.conj(np.swapaxes(W, -1, -2))
 
 
-def _exp_i_hermitian(H: np.ndarray, eps: float) -> np.ndarray:
+def _exp_i_hermitian(H: np.ndarray, eps: float, fallback: bool = True):
     """exp(i Q), Q = eps H traceless Hermitian 3x3, by the Cayley-Hamilton closed
     form of Morningstar & Peardon, Phys. Rev. D 69 (2004) 054501:
     exp(iQ) = f0 + f1 Q + f2 Q^2 with f_j from c0 = det Q, c1 = tr Q^2 / 2.
     Stacks whose spectrum is close to degenerate fall back to the
-    eigendecomposition."""
+    eigendecomposition; with fallback=False they are left for the caller, and
+    (U, mask of those entries) is returned.  Only elementwise numpy runs here
+    unless the fallback is taken."""
     shape = H.shape[:-2]
     Q = eps * H.reshape(-1, 9)
     q = [[np.ascontiguousarray(Q[:, 3 * i + j]) for j in range(3)] for i in range(3)]
@@ -108,6 +113,8 @@ def _exp_i_hermitian(H: np.ndarray, eps: float) -> np.ndarray:
                 e += f0
             U[:, 3 * i + j] = e
     U = U.reshape(shape + (3, 3))
+    if not fallback:
+        return U, bad.reshape(shape)
     if np.any(bad):
         U[bad.reshape(shape)] = _exp_i_hermitian_eigh(H[bad.reshape(shape)], eps)
     return U
@@ -120,16 +127,41 @@ def random_su3_links(dims, eps: float, seed: int = 0, chunk: int = 1 << 20) -> n
     gives unit links.  The eight normals per link are consumed site-major,
     then direction, then generator index.
     """
+    from concurrent.futures import ThreadPoolExecutor
+
     V = volume(dims)
     rng = np.random.default_rng(seed)
     lam = gell_mann() / 2.0
     U = np.empty((V * 4, 3, 3), dtype=np.complex128)
     nlinks = V * 4
-    for start in range(0, nlinks, chunk):
-        stop = min(nlinks, start + chunk)
-        h = rng.standard_normal((stop - start, 8))
-        H = (h.astype(np.complex128) @ lam.reshape(8, 9)).reshape(-1, 3, 3)
-        U[start:stop] = _exp_i_hermitian(H, eps)
+
+    def fill(start, H):
+        Uc, bad = _exp_i_hermitian(H, eps, fallback=False)
+        U[start:start + len(H)] = Uc
+        return start, H, bad
+
+    def finish(job):
+        # the rare eigendecomposition fallback runs here, on the calling
+        # thread, like every BLAS/LAPACK call of this function
+        start, H, bad = job.result()
+        if np.any(bad):
+            U[start:start + len(H)][bad] = _exp_i_hermitian_eigh(H[bad], eps)
+
+    # the normals and H (a matrix product) are formed in order on this
+    # thread; the closed-form exponentials (elementwise numpy, which releases
+    # the GIL) run on a few worker threads
+    workers = max(1, min(8, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as ex:
+        jobs = []
+        for start in range(0, nlinks, chunk):
+            stop = min(nlinks, start + chunk)
+            h = rng.standard_normal((stop - start, 8))
+            H = (h.astype(np.complex128) @ lam.reshape(8, 9)).reshape(-1, 3, 3)
+            jobs.append(ex.submit(fill, start, H))
+            if len(jobs) >= 2 * workers:
+                finish(jobs.pop(0))
+        for j in jobs:
+            finish(j)
     return U.reshape(V, 4, 3, 3)
 
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import BC, REL_TOL_SAP, Lattice, rel, to_dev, to_host
+from gpu_util import BC, Lattice, check_sap, to_dev, to_host
 from paper_1710_07041_amd import synth
 from test_gpu_solver import gpu_solve
 
@@ -38,7 +38,7 @@ def test_sap_eo_matches_oracle(lat, prec, ncy, nmr):
     m0 = -0.2
     ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0, eta, ncy, nmr, BC, eo=True)
     out = gpu_sap_eo(lat, eta, m0, ncy, nmr, prec)
-    assert rel(out, ref) <= REL_TOL_SAP[prec]
+    check_sap(out, ref, "eo-" + prec, f"{'x'.join(map(str, lat.dims))} ncy={ncy} nmr={nmr}")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -50,7 +50,7 @@ def test_sap_eo_multi_rhs(lat, prec):
     out = gpu_sap_eo(lat, eta, m0, 2, 4, prec, nrhs=n)
     for r in range(n):
         ref = oracle.sap(lat.dims, (4, 4, 4, 4), lat.U, lat.C, m0[r], eta[r], 2, 4, BC, eo=True)
-        assert rel(out[r], ref) <= REL_TOL_SAP[prec]
+        check_sap(out[r], ref, "eo-" + prec, f"{'x'.join(map(str, lat.dims))} multi-rhs r={r}")
         if prec == "f64":
             assert np.array_equal(out[r], gpu_sap_eo(lat, eta[r], m0[r], 2, 4, prec))
 

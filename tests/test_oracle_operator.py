@@ -237,6 +237,32 @@ def test_apply_D_sites_matches_field(rand_field):
     assert np.array_equal(part, full[sites])
 
 
+def test_apply_D_sites_multi_and_chunked_residual(rand_field):
+    """Several vectors at once equal the whole-lattice operator on each
+    (bitwise); the chunked residual equals ||b - D x|| / ||b|| formed from the
+    whole-lattice operator, and tells a perturbed solution apart."""
+    dims, U = rand_field
+    C = oracle.clover_field(dims, U, 1.0)
+    V = synth.volume(dims)
+    xs = synth.gaussian_spinor(dims, nrhs=3, seed=11)
+    sites = np.array([0, 7, 33, V // 2, V - 1])
+    part = oracle.apply_D_sites_multi(dims, U, 1.0, -0.2, xs, sites, BC)
+    for k in range(3):
+        assert np.array_equal(part[k], oracle.apply_D(dims, U, C, -0.2, xs[k], BC)[sites])
+    b = synth.gaussian_spinor(dims, seed=12)
+    res = oracle.rel_residuals(dims, U, 1.0, -0.2, b, xs, BC, chunk=V // 3 + 1)
+    for k in range(3):
+        ref = np.linalg.norm(b - oracle.apply_D(dims, U, C, -0.2, xs[k], BC)) / np.linalg.norm(b)
+        assert abs(res[k] - ref) <= 1e-14 * ref
+    # D x = b exactly for x = D^-1 b would give 0; a solution that is exact up
+    # to one site's perturbation gives that site's hop-weighted error
+    x = xs[0].copy()
+    bx = oracle.apply_D(dims, U, C, -0.2, x, BC)
+    x[5, 1, 2] += 1e-6
+    r = oracle.rel_residuals(dims, U, 1.0, -0.2, bx, x[None], BC, chunk=V // 2)[0]
+    assert 1e-8 < r * np.linalg.norm(bx) < 1e-5
+
+
 def test_DBB_is_restriction():
     """For psi supported on B: (D psi)_B = D_BB psi_B; off the block D_BB is zero."""
     dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
