@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define DD_ABI_VERSION 4
+#define DD_ABI_VERSION 5
 #define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
 
 typedef enum {
@@ -72,7 +72,9 @@ typedef enum {
     DD_OOM = 2,           /* a device allocation failed                           */
     DD_HIP_ERROR = 3,     /* a HIP runtime call failed                            */
     DD_NOT_CONVERGED = 4, /* max restarts reached; x holds the best iterate       */
-    DD_BREAKDOWN = 5,     /* Arnoldi breakdown without convergence                */
+    DD_BREAKDOWN = 5,     /* the Krylov space closed on a singular projection of D
+                             without convergence (e.g. b in the null space of a
+                             singular D); x holds the last iterate               */
     DD_NAN = 6,           /* NaN or Inf found in an input or a residual           */
     DD_NO_FIELD = 7       /* the call needs a gauge field that was never set      */
 } dd_status;
@@ -109,13 +111,18 @@ int dd_abi_version(void);
 void dd_default_params(dd_params *p);
 
 /* Create a context for a Lx x Ly x Lz x Lt lattice on the current HIP device.
- *   dims   lattice extents; each a multiple of 4 (the Schwarz block extent);
+ *   dims   lattice extents; each a multiple of the block extent;
+ *   block  Schwarz block extents (Sec. 3.1: the MR inversion runs within
+ *          these domains); NULL or {4,4,4,4} -- the only blocking the kernels
+ *          implement (one 256-thread workgroup per 4^4 block, one site per
+ *          thread); any other value is DD_INVALID_ARG;
  *   bcs    fermion boundary sign per direction, +1 or -1 (e.g. {1,1,1,-1});
  *   stream hipStream_t to enqueue on (NULL = the null stream);
  *   out    receives the context.
- * DD_INVALID_ARG if an extent is not a positive multiple of 4 or a direction
- * has an odd number (>1) of blocks; DD_OOM / DD_HIP_ERROR on device failure. */
-dd_status dd_create(const int dims[4], const int bcs[4], void *stream, dd_ctx **out);
+ * DD_INVALID_ARG if an extent is not a positive multiple of 4, a direction
+ * has an odd number (>1) of blocks, or block is not 4^4; DD_OOM /
+ * DD_HIP_ERROR on device failure. */
+dd_status dd_create(const int dims[4], const int block[4], const int bcs[4], void *stream, dd_ctx **out);
 
 /* Release the context and every device buffer it owns (synchronises). */
 dd_status dd_destroy(dd_ctx *ctx);
@@ -284,11 +291,13 @@ dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m
                            long *request_id);
 
 /* *done = 1 when the request has finished; then info (host, nrhs entries,
- * may be NULL) and latency_ms (may be NULL) are filled and the request's
- * status is returned. */
+ * may be NULL) and latency_ms (may be NULL) are filled, the request's status
+ * is returned and the server forgets the request (its id is then unknown:
+ * DD_INVALID_ARG).  *done = 0 and DD_OK while it runs. */
 dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info *info, double *latency_ms);
 
-/* Block until the request finishes; as dd_server_poll otherwise. */
+/* Block until the request finishes; as dd_server_poll otherwise (the request
+ * is forgotten on return).  Safe while other threads submit. */
 dd_status dd_server_wait(dd_server *s, long request_id, dd_solve_info *info, double *latency_ms);
 
 /* Latency percentiles and throughput of the requests finished so far. */
@@ -299,6 +308,21 @@ const char *dd_server_last_error(const dd_server *s);
 
 /* Stop the worker (pending requests are abandoned) and free everything. */
 dd_status dd_server_destroy(dd_server *s);
+
+/* ---------------------------------------------------------------------------
+ * Test hook
+ * ---------------------------------------------------------------------------
+ * FP16 range (Sec. 3.1 stores part of the data in half precision): dd_solve
+ * scales each right-hand side into FP16's range before the smoother, and if
+ * a smoother output still turns non-finite the outer iteration drops that
+ * step's column, restarts from the last FP64 iterate and runs the FP16
+ * smoother in FP32 from then on.  This hook exercises that path from the
+ * host: the next `count` FP16 smoother applications of dd_solve on ctx (all
+ * of them for count < 0; none for 0, the default) get an FP16 infinity in
+ * the first entry of each active right-hand side's output.  A solve under
+ * the hook still converges, in FP32, if the fallback works; it never
+ * affects FP32/FP64 smoothers.  DD_INVALID_ARG for a NULL context. */
+dd_status dd_debug_poison_half_smoother(dd_ctx *ctx, int count);
 
 /* ---------------------------------------------------------------------------
  * Measurement (optional; used to price kernels against the hardware roofline)

@@ -76,7 +76,7 @@ void dd_default_params(dd_params *p)
 
 const char *dd_last_error(const dd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
-dd_status dd_create(const int dims[4], const int bcs[4], void *stream, dd_ctx **out)
+dd_status dd_create(const int dims[4], const int block[4], const int bcs[4], void *stream, dd_ctx **out)
 {
     g_create_error.clear();
     if (!dims || !bcs || !out) {
@@ -84,6 +84,12 @@ dd_status dd_create(const int dims[4], const int bcs[4], void *stream, dd_ctx **
         return DD_INVALID_ARG;
     }
     *out = nullptr;
+    if (block)
+        for (int mu = 0; mu < 4; ++mu)
+            if (block[mu] != 4) {
+                g_create_error = "dd_create: only 4x4x4x4 Schwarz blocks are implemented";
+                return DD_INVALID_ARG;
+            }
     dd::GeomHost g{};
     long V = 1;
     for (int mu = 0; mu < 4; ++mu) {
@@ -334,6 +340,13 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
         DD_TRY(set_device(ctx));
         return dd::solve(ctx, m0, b, x, nrhs, p, info);
     });
+}
+
+dd_status dd_debug_poison_half_smoother(dd_ctx *ctx, int count)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    ctx->debug_poison_half = count < 0 ? -1 : count;
+    return DD_OK;
 }
 
 dd_status dd_profile_enable(dd_ctx *ctx, int enable)

@@ -125,6 +125,7 @@ struct dd_ctx {
     bool link_su3 = false; // every link is SU(3) to FP64 rounding (checked at ingest)
     bool link_r12 = false; // kernels read two rows per link and rebuild the third
     bool sap_half_fields = false; // the plain FP32 smoother reads the FP16 links and clover
+    int debug_poison_half = 0;    // test hook: FP16 smoother outputs to poison (-1: all)
     dd::DevBuf links[3];  // blocked links per dd_prec
     dd::DevBuf clover[3]; // blocked clover per dd_prec
     dd::DevBuf colour_blocks[2]; // int block ids of each colour, XCD-friendly order

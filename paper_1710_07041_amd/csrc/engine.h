@@ -42,6 +42,9 @@ struct SlotState {
     double qr(int m, int n);
     // y = R^-1 g over n columns (ENGINE_MAXM entries, the rest zero)
     void solve_y(int m, int n, std::complex<double> *y) const;
+    // whether the QR factor of the leading n columns has a zero on its
+    // diagonal (the projected least-squares problem has no unique solution)
+    bool singular(int m, int n) const;
     dd_solve_info info{};
     long owner = 0; // caller's tag (request id) and right-hand-side index
     int owner_rhs = 0;

@@ -426,6 +426,14 @@ __global__ __launch_bounds__(TPB) void k_combine(double2 *__restrict__ x, const 
 }
 
 // FP16 smoother output -> FP32 basis vector: Z[off_r] = out / scale_r
+// Test hook: an FP16 infinity in the first entry of every active slot's
+// smoother output, as if FP16's range had been exceeded.
+__global__ void k_poison_half(__half2 *__restrict__ p, const int *__restrict__ active, int nrhs)
+{
+    const int r = threadIdx.x;
+    if (r < nrhs && active[r]) p[(long)r * 12 * BS] = __halves2half2(__ushort_as_half(0x7C00), __ushort_as_half(0x7C00));
+}
+
 __global__ __launch_bounds__(TPB) void k_unscale(const __half2 *__restrict__ in, float2 *__restrict__ Z,
                                                  const long *__restrict__ zoff, const double *__restrict__ scl,
                                                  const int *__restrict__ active, int nblocks, int nrhs)
@@ -691,6 +699,11 @@ struct Engine::Impl {
             DD_TRY(run_sap(ctx, nullptr, W, lp.p, Z.p, P.ncy, P.nmr, DD_F32, &ss, P.sap_eo));
         } else {
             DD_TRY(run_sap(ctx, nullptr, W, lp.p, sapout.p, P.ncy, P.nmr, DD_F16, &ss, P.sap_eo));
+            if (ctx->debug_poison_half != 0) {
+                k_poison_half<<<1, 64, 0, st()>>>(sapout.as<__half2>(), d_active(), W);
+                DD_HIP_TRY(hipGetLastError());
+                if (ctx->debug_poison_half > 0) --ctx->debug_poison_half;
+            }
             ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 12.0, 2.0 * vlen);
             k_unscale<<<grid(), TPB, 0, st()>>>(sapout.as<__half2>(), Z.as<float2>(), d_psi_off(), scl.as<double>(),
                                                 d_active(), ctx->g.nblocks, W);
@@ -724,6 +737,13 @@ double SlotState::qr(int m, int n)
         g[k] = cs[k] * g[k];
     }
     return std::abs(g[n]);
+}
+
+bool SlotState::singular(int m, int n) const
+{
+    for (int k = 0; k < n; ++k)
+        if (R[(size_t)k * m + k] == Z64(0.0)) return true;
+    return false;
 }
 
 void SlotState::solve_y(int m, int n, std::complex<double> *y) const
@@ -969,7 +989,7 @@ Status Engine::launch_step()
     }
     DD_TRY(e.upload(h));
     const int bucket = pick_bucket(jmax);
-    const bool use_graph = e.P.graphs && !e.ctx->prof.on;
+    const bool use_graph = e.P.graphs && !e.ctx->prof.on && e.ctx->debug_poison_half == 0;
     if (use_graph) {
         // the kernels' arguments also depend on the link format
         const int key = ((bucket * 4 + e.sap_prec) * 2 + (e.ctx->link_r12 ? 1 : 0)) * 2 + (e.ctx->sap_half_fields ? 1 : 0);
@@ -1062,6 +1082,17 @@ Status Engine::finish_step()
         const double est = s.qr(m, ncols);
         if (beta == 0.0 || !(est / s.bnorm > e.P.tol) || ncols == m) end = true;
         s.j = ncols;
+        if (end && s.singular(m, ncols)) {
+            // the Krylov space closed (beta = 0, or p_j in the span of V) on a
+            // singular projection of D: no correction from this space
+            // minimises the residual uniquely, and restarting would rebuild
+            // the same space.  Arnoldi breakdown without convergence; x keeps
+            // the last iterate, rel_residual its true residual.
+            s.state = SLOT_DONE;
+            s.info.status = DD_BREAKDOWN;
+            s.cycle_len = 0;
+            continue;
+        }
         if (end) {
             // end of this slot's cycle: y = R^-1 g, then x += Z y
             s.solve_y(m, ncols, yr);

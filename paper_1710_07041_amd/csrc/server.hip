@@ -278,7 +278,7 @@ dd_status dd_server_add_field(dd_server *s, const int dims[4], const int bcs[4],
         s->err = "server: stream creation failed";
         return DD_HIP_ERROR;
     }
-    dd_status st = dd_create(dims, bcs, f.stream, &f.ctx);
+    dd_status st = dd_create(dims, nullptr, bcs, f.stream, &f.ctx);
     if (st != DD_OK) {
         s->err = std::string("server: ") + dd_last_error(nullptr);
         (void)hipStreamDestroy(f.stream);
@@ -378,6 +378,21 @@ dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m
     return DD_OK;
 }
 
+namespace {
+// Hand a finished request's results to the caller and forget it (the caller
+// holds s->mu).
+dd_status deliver(dd_server *s, long request_id, dd_solve_info *info, double *latency_ms)
+{
+    auto it = s->reqs.find(request_id);
+    const dd_server::Request &r = it->second;
+    if (info) std::memcpy(info, r.info.data(), sizeof(dd_solve_info) * r.nrhs);
+    if (latency_ms) *latency_ms = (r.t_done - r.t_submit) * 1e3;
+    const dd_status st = (dd_status)r.status;
+    s->reqs.erase(it);
+    return st;
+}
+} // namespace
+
 dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info *info, double *latency_ms)
 {
     if (!s || !done) return DD_INVALID_ARG;
@@ -385,11 +400,7 @@ dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return DD_INVALID_ARG;
     *done = it->second.complete ? 1 : 0;
-    if (it->second.complete) {
-        if (info) std::memcpy(info, it->second.info.data(), sizeof(dd_solve_info) * it->second.nrhs);
-        if (latency_ms) *latency_ms = (it->second.t_done - it->second.t_submit) * 1e3;
-        return (dd_status)it->second.status;
-    }
+    if (it->second.complete) return deliver(s, request_id, info, latency_ms);
     return DD_OK;
 }
 
@@ -399,10 +410,11 @@ dd_status dd_server_wait(dd_server *s, long request_id, dd_solve_info *info, dou
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return DD_INVALID_ARG;
-    s->cv_done.wait(lk, [&] { return it->second.complete; });
-    if (info) std::memcpy(info, it->second.info.data(), sizeof(dd_solve_info) * it->second.nrhs);
-    if (latency_ms) *latency_ms = (it->second.t_done - it->second.t_submit) * 1e3;
-    return (dd_status)it->second.status;
+    // an element reference survives the rehash that a concurrent submit may
+    // cause; an iterator does not
+    const dd_server::Request &r = it->second;
+    s->cv_done.wait(lk, [&] { return r.complete; });
+    return deliver(s, request_id, info, latency_ms);
 }
 
 dd_status dd_server_get_stats(dd_server *s, dd_server_stats *out)

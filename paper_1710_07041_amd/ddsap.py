@@ -38,7 +38,8 @@ DD_MAX_RHS = 16
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_sap_half_fields", "dd_sap_half_fields", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
-    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_profile_enable", "dd_profile_read",
+    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_debug_poison_half_smoother", "dd_profile_enable",
+    "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
     "dd_server_destroy",
@@ -80,7 +81,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _sigs = {
     "dd_abi_version": ([], _i),
     "dd_default_params": ([ctypes.POINTER(dd_params)], None),
-    "dd_create": ([_ip, _ip, _vp, ctypes.POINTER(_vp)], _i),
+    "dd_create": ([_ip, _ip, _ip, _vp, ctypes.POINTER(_vp)], _i),
     "dd_destroy": ([_vp], _i),
     "dd_last_error": ([_vp], ctypes.c_char_p),
     "dd_synchronize": ([_vp], _i),
@@ -98,6 +99,7 @@ _sigs = {
     "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_sap_eo": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
+    "dd_debug_poison_half_smoother": ([_vp, _i], _i),
     "dd_profile_enable": ([_vp, _i], _i),
     "dd_server_default_config": ([ctypes.POINTER(dd_server_config)], None),
     "dd_server_create": ([ctypes.POINTER(dd_server_config), ctypes.POINTER(_vp)], _i),
@@ -148,14 +150,15 @@ def _masses(m0, nrhs):
 class Context:
     """One lattice on the current HIP device (wraps dd_ctx)."""
 
-    def __init__(self, dims, bcs=(1, 1, 1, -1), stream=None):
+    def __init__(self, dims, bcs=(1, 1, 1, -1), stream=None, block=(4, 4, 4, 4)):
         import torch
         self.dims = tuple(int(d) for d in dims)
         self.volume = int(np.prod(self.dims))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._h = _vp()
-        st = _lib.dd_create((ctypes.c_int * 4)(*self.dims), (ctypes.c_int * 4)(*bcs), _vp(stream),
+        blk = None if block is None else (ctypes.c_int * 4)(*block)
+        st = _lib.dd_create((ctypes.c_int * 4)(*self.dims), blk, (ctypes.c_int * 4)(*bcs), _vp(stream),
                             ctypes.byref(self._h))
         if st != DD_OK:
             raise DDError(st, _lib.dd_last_error(None).decode())
@@ -254,6 +257,11 @@ class Context:
             raise DDError(st, _lib.dd_last_error(self._h).decode())
         return st, out
 
+    def debug_poison_half_smoother(self, count):
+        """Test hook: the next `count` FP16 smoother outputs of solve() (all for
+        count < 0) get a non-finite entry, which must trigger the FP32 fallback."""
+        self._check(_lib.dd_debug_poison_half_smoother(self._h, int(count)))
+
     def profile_enable(self, on=True):
         self._check(_lib.dd_profile_enable(self._h, 1 if on else 0))
 
@@ -326,6 +334,7 @@ class Server:
         st = _lib.dd_server_poll(self._h, int(rid), ctypes.byref(done), infos, ctypes.byref(lat))
         if not done.value:
             return False, None, None, None
+        self._live.pop(rid, None)
         return True, st, [{k: getattr(i, k) for k, _ in dd_solve_info._fields_} for i in infos], lat.value
 
     def wait(self, rid):
