@@ -2,19 +2,27 @@
 """Benchmark: Dslash GB/s against the HBM roofline and time-to-1e-10 of the
 SAP-preconditioned FGMRES solve (mixed precision vs FP64) on one MI355X.
 
-One step = one complete solve of the workload: FP64 FGMRES(20) outer iteration
-(operator, CGS2 orthogonalisation, reductions, true-residual restarts) with
-the red-black SAP smoother (4^4 blocks, 4 MR steps, 4 cycles) in FP32 --
-every stage of the hot path.  Inputs (gauge field, clover, right-hand side)
-are resident in HBM before the timed region starts.
+Default workload: the 48^3x96 lattice (eps = 0.6, csw = 1, m0 = -0.38), one
+Gaussian right-hand side, the red-black SAP smoother (4^4 blocks, 4 MR steps,
+12 cycles) with FP16 link/clover/spinor storage and FP32 arithmetic inside
+FP64 FGMRES(20), tolerance 1e-10; the FP64 GPU path (the same algorithm with
+an FP64 smoother) is timed alongside.  One step = one complete solve: FP64
+outer iteration (operator, CGS2 orthogonalisation, reductions, true-residual
+restarts) with the smoother -- every stage of the hot path.  Inputs (gauge
+field, clover, right-hand side) are resident in HBM before the timed region
+starts.
 
 The JSON line reports
   value            algorithmic GB/s of the FP64 Wilson-clover operator launches
                    inside the timed solves (HIP events on the launch stream);
-  roofline         the kernel class that dominates the step time;
-  roofline_dslash  the operator itself, against 8 TB/s HBM;
-  time_to_solution mixed (FP32 SAP) vs the FP64 GPU path (FP64 SAP);
-  cpu_baseline     the FP64 CPU oracle on a bounded sample, same unit.
+  roofline         the kernel class that dominates the step time, priced with
+                   the survey's algorithmic count (10,584 flops per site and
+                   SAP cycle), the kernel's own count beside it;
+  roofline_dslash  the operator itself, against 8 TB/s HBM and against the
+                   measured device-copy bandwidth;
+  time_to_solution mixed vs the FP64 GPU path (median and min of the repeats);
+  cpu_baseline     the FP64 CPU oracle on bounded samples: its operator (same
+                   unit as value), one SAP cycle, and a full 8^4 solve.
 """
 from __future__ import annotations
 
@@ -62,12 +70,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--fp64-steps", type=int, default=1, help="FP64-smoother solves timed alongside")
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp64-steps", type=int, default=3, help="FP64-smoother solves timed alongside")
     ap.add_argument("--eo-steps", type=int, default=1,
                     help="solves with the even-odd preconditioned smoother (mixed and FP64) timed alongside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="budget of the oracle operator sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle operator on the workload lattice, one SAP cycle there and the full "
+                         "32^3x64 solve (minutes of host time)")
     ap.add_argument("--serve", action="store_true", help="run the continuous-batching serving workload instead")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-budget-gb", type=int, default=120)
@@ -79,9 +90,13 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(seconds):
-    """The FP64 oracle's operator on a bounded sample: the 16^3x32 lattice (the
-    paper's single-chip lattice) with the workload's field recipe."""
+def cpu_baseline(seconds, workload=None, full=False):
+    """The FP64 oracle on bounded samples, on every host core it is given:
+    its operator on the 16^3x32 lattice (the paper's single-chip lattice, the
+    workloads' field recipe) in the metric's unit, one SAP cycle (nmr = 4) on
+    the same lattice, and the full 8^4 solve (FGMRES(20) with 12 SAP cycles
+    per preconditioner call, tol 1e-10).  With full: the operator and one SAP
+    cycle on the workload's own lattice, and the complete 32^3x64 solve."""
     import oracle
     from paper_1710_07041_amd import synth
     dims = (16, 16, 16, 32)
@@ -91,17 +106,66 @@ def cpu_baseline(seconds):
     V = synth.volume(dims)
     t0 = time.perf_counter()
     n = 0
+    times = []
     while True:
+        t1 = time.perf_counter()
         oracle.apply_D(dims, U, C, -0.35, psi)
+        times.append(time.perf_counter() - t1)
         n += 1
-        if time.perf_counter() - t0 >= seconds:
+        if time.perf_counter() - t0 >= seconds and n >= 3:
             break
-    dt = (time.perf_counter() - t0) / n
-    return {"value": round(V * 192 * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle Wilson-clover operator on a 16^3x32 lattice (eps=0.5, csw=1), {n} applications "
-                      f"in {dt * n:.1f} s; algorithmic 192 reals/site as on the GPU",
-            "ms_per_apply": round(dt * 1e3, 3)}
+    dt = float(np.median(times))
+    sap = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        oracle.sap(dims, (4, 4, 4, 4), U, C, -0.35, psi, 1, 4)
+        sap.append(time.perf_counter() - t1)
+    sap_s = float(np.median(sap))
+    # the 8^4 workload, solved completely
+    d1 = (8, 8, 8, 8)
+    U1 = synth.random_su3_links(d1, 0.3, seed=0)
+    C1 = oracle.clover_field(d1, U1, 1.0)
+    b1 = synth.gaussian_spinor(d1, seed=0)
+    t1 = time.perf_counter()
+    _, info1 = oracle.fgmres(d1, (4, 4, 4, 4), U1, C1, -0.2, b1, m=20, tol=1e-10, ncy=12, nmr=4)
+    c1_s = time.perf_counter() - t1
+    out = {"value": round(V * 192 * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"FP64 oracle Wilson-clover operator on a 16^3x32 lattice (eps=0.5, csw=1), median of {n} "
+                     f"applications; algorithmic 192 reals/site as on the GPU",
+           "ms_per_apply": round(dt * 1e3, 3),
+           "gflops_operator": round(1848.0 * V / dt / 1e9, 2),
+           "sap_cycle_16x16x16x32_ms": round(sap_s * 1e3, 1),
+           "sap_cycle_gflops": round(10584.0 * V / sap_s / 1e9, 2),
+           "solve_8x8x8x8": {"time_s": round(c1_s, 3), "iterations": info1["iterations"],
+                             "rel_residual": info1["rel_residual"],
+                             "params": "FGMRES(20), SAP ncy=12 nmr=4, m0=-0.2, eps=0.3, tol 1e-10"}}
+    if full and workload is not None:
+        wd = workload["dims"]
+        Vw = synth.volume(wd)
+        Uw = synth.random_su3_links(wd, workload["eps"], seed=0)
+        Cw = oracle.clover_field(wd, Uw, workload["csw"])
+        pw = synth.gaussian_spinor(wd, seed=1)
+        t1 = time.perf_counter()
+        oracle.apply_D(wd, Uw, Cw, workload["m0"], pw)
+        dw = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.sap(wd, (4, 4, 4, 4), Uw, Cw, workload["m0"], pw, 1, 4)
+        sw = time.perf_counter() - t1
+        out["workload_lattice"] = {"lattice": "x".join(map(str, wd)), "apply_ms": round(dw * 1e3, 1),
+                                   "apply_gbs": round(Vw * 192 * 8 / dw / 1e9, 3),
+                                   "sap_cycle_ms": round(sw * 1e3, 1)}
+        del Uw, Cw, pw
+        d2 = (32, 32, 32, 64)
+        U2 = synth.random_su3_links(d2, 0.5, seed=0)
+        C2 = oracle.clover_field(d2, U2, 1.0)
+        b2 = synth.gaussian_spinor(d2, seed=0)
+        t1 = time.perf_counter()
+        _, info2 = oracle.fgmres(d2, (4, 4, 4, 4), U2, C2, -0.35, b2, m=20, tol=1e-10, ncy=12, nmr=4)
+        out["solve_32x32x32x64"] = {"time_s": round(time.perf_counter() - t1, 2), "iterations": info2["iterations"],
+                                    "rel_residual": info2["rel_residual"],
+                                    "params": "FGMRES(20), SAP ncy=12 nmr=4, m0=-0.35, eps=0.5, tol 1e-10"}
+    return out
 
 
 def make_rhs(w, V, dims):
@@ -123,19 +187,24 @@ def roofline_entry(name, st, peak_gbs=HBM_PEAK_GBS):
             "frac_hbm": round(gbs / peak_gbs, 4)}
 
 
-def dslash_standalone(ctx, dims, reps=20):
-    """The operator alone in every precision, for one and for 12 fused
-    right-hand sides, timed with HIP events on the context stream: GB/s vs the
-    roofline."""
+def dslash_standalone(ctx, dims, reps=20, copy_gbs=None):
+    """The operator alone in every precision, for one and (up to 32^3x64) for
+    12 fused right-hand sides, timed with HIP events on the context stream:
+    GB/s vs the roofline (and vs the measured copy bandwidth)."""
     import torch
     from paper_1710_07041_amd import synth
     res = {}
-    for prec, n in (("f64", 1), ("f32", 1), ("f16", 1), ("f64", 12), ("f32", 12), ("f16", 12)):
-        psi = synth.gaussian_spinor(dims, nrhs=n, seed=3)
-        x = torch.from_numpy(psi).to("cuda")
+    V = synth.volume(dims)
+    cases = [("f64", 1), ("f32", 1), ("f16", 1)]
+    if V <= 32 ** 3 * 64:
+        cases += [("f64", 12), ("f32", 12), ("f16", 12)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    for prec, n in cases:
+        x = torch.randn((n, V, 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
         xb, yb = ctx.empty_blocked(prec, n), ctx.empty_blocked(prec, n)
         ctx.pack(x, xb, prec, n)
-        del x, psi
+        del x
         m0 = np.full(n, -0.35)
         ctx.apply_D(m0, xb, yb, prec, n)
         ctx.profile_enable(True)
@@ -146,7 +215,8 @@ def dslash_standalone(ctx, dims, reps=20):
         (name, v), = st.items()
         e = roofline_entry(name, v)
         res[f"{prec}_x{n}"] = {"gbs": e["gbs"], "frac": e["frac_hbm"], "avg_ms": e["avg_ms"],
-                               "gflops": round(e["tflops"] * 1e3, 1)}
+                               "gflops": round(e["tflops"] * 1e3, 1),
+                               **({"frac_of_copy": round(e["gbs"] / copy_gbs, 4)} if copy_gbs else {})}
         del xb, yb
         torch.cuda.empty_cache()
     return res
@@ -295,12 +365,23 @@ def main():
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
 
-    # a plain 1 GiB device copy: the reference a counter run scales FETCH/WRITE by
+    # a plain 1 GiB device copy: the reference a counter run scales FETCH/WRITE
+    # by, and the achievable-bandwidth line (2 GiB moved per copy; median of 10)
     ca = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
     cb = torch.empty_like(ca)
     cb.copy_(ca)
     torch.cuda.synchronize()
+    ct = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cb.copy_(ca)
+        e1.record()
+        e1.synchronize()
+        ct.append(e0.elapsed_time(e1) * 1e-3)
+    copy_gbs = 2.0 * ca.numel() * 4 / float(np.median(ct)) / 1e9
     del ca, cb
+    log(f"device copy: {copy_gbs:.0f} GB/s")
 
     for i in range(args.warmup):
         info = one_solve(w["sap"])
@@ -309,9 +390,11 @@ def main():
     ctx.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, tsteps = [], []
     for i in range(args.steps):
-        infos.append(one_solve(w["sap"]))
+        t1 = time.perf_counter()
+        infos.append(one_solve(w["sap"]))  # dd_solve synchronises
+        tsteps.append(time.perf_counter() - t1)
         log(f"step {i}: {infos[-1][0]['iterations']} iterations, residual {infos[-1][0]['rel_residual']:.2e}")
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / args.steps
@@ -321,15 +404,16 @@ def main():
     # FP64 GPU path (FP64 smoother), same algorithm, timed alongside
     t64 = None
     info64 = None
+    t64s = []
     if args.fp64_steps > 0:
         one_solve("f64")
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
         for i in range(args.fp64_steps):
+            t1 = time.perf_counter()
             info64 = one_solve("f64")
-        torch.cuda.synchronize()
-        t64 = (time.perf_counter() - t0) / args.fp64_steps
-        log(f"fp64 path: {info64[0]['iterations']} iterations, {t64 * 1e3:.1f} ms")
+            t64s.append(time.perf_counter() - t1)
+        t64 = float(np.median(t64s))
+        log(f"fp64 path: {info64[0]['iterations']} iterations, median {t64 * 1e3:.1f} ms of {len(t64s)}")
 
     # the even-odd preconditioned smoother (a refinement beyond the paper's
     # plain block MR), mixed and FP64, timed alongside
@@ -357,7 +441,7 @@ def main():
         even_odd["mixed_speedup_over_plain"] = round(t_mixed / even_odd["mixed"]["time_s"], 3)
 
     # sensitivity of the mixed solve to the SAP cycles per preconditioner call
-    # (the paper leaves the count open; 4 is the default)
+    # (the paper leaves the count open; 12 is the default)
     ncy_scan = None
     if args.ncy_scan:
         ncy_scan = {}
@@ -387,7 +471,7 @@ def main():
         del bs, xs
         log(f"{nrhs} right-hand sides one at a time: {sequential * 1e3:.1f} ms")
 
-    standalone = None if args.no_standalone else dslash_standalone(ctx, dims)
+    standalone = None if args.no_standalone else dslash_standalone(ctx, dims, copy_gbs=copy_gbs)
     log(f"operator alone: {standalone}")
 
     # operator launches inside the timed solves
@@ -403,11 +487,25 @@ def main():
     dom = max(prof, key=lambda k: prof[k]["total_ms"])
     rdom = roofline_entry(dom, prof[dom])
     if dom.startswith("sap"):
-        # smoother: arithmetic intensity above the FP32 ridge -> priced against the vector ALU peak
-        roof = {"bound": "alu", "kernel": dom, "achieved": rdom["tflops"], "peak": round(FP32_UNPACKED_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(rdom["tflops"] / FP32_UNPACKED_TFLOPS, 4), "traffic": None,
-                "peak_published": FP32_VEC_TFLOPS, "frac_published": round(rdom["tflops"] / FP32_VEC_TFLOPS, 4),
-                "hbm_gbs": rdom["gbs"], "hbm_frac": rdom["frac_hbm"], "avg_ms": rdom["avg_ms"]}
+        # smoother: arithmetic intensity above the FP32 ridge -> priced against
+        # the vector ALU peak.  Algorithmic work per launch: the survey's
+        # count, 10,584 flops per site and SAP cycle (four MR steps of 2,184
+        # and the block residual of 1,848), times the V/2 sites x nrhs one
+        # colour sweep covers; the kernel's own count (the carried residual
+        # needs no residual application) beside it.
+        nmr = ddsap.default_params().nmr
+        alg_flops = V / 2 * nrhs * (nmr * 2184.0 + 1848.0)
+        alg_tf = alg_flops / (rdom["avg_ms"] * 1e-3) / 1e12
+        peak = FP32_UNPACKED_TFLOPS if not dom.endswith("f64") else FP64_VEC_TFLOPS
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(alg_tf, 2), "peak": round(peak, 1),
+                "unit": "TFLOP/s", "frac": round(alg_tf / peak, 4), "traffic": None,
+                "flops_per_launch": alg_flops, "flop_count": "10584 per site and SAP cycle (nmr=4)",
+                "achieved_kernel_count": rdom["tflops"], "frac_kernel_count": round(rdom["tflops"] / peak, 4),
+                "kernel_flops_per_launch": rdom["flops_per_launch"],
+                **({"peak_published": FP32_VEC_TFLOPS, "frac_published": round(alg_tf / FP32_VEC_TFLOPS, 4)}
+                   if not dom.endswith("f64") else {}),
+                "hbm_gbs": rdom["gbs"], "hbm_frac": rdom["frac_hbm"], "avg_ms": rdom["avg_ms"],
+                "launches": rdom["launches"]}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": rdom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": rdom["frac_hbm"], "traffic": None, "avg_ms": rdom["avg_ms"]}
@@ -431,7 +529,7 @@ def main():
                      "gbs": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] > 0 else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds, w, args.cpu_full)
 
     out = {
         "metric": "Dslash GB/s & % HBM roofline; time-to-1e-10 SAP-FGMRES solve (mixed vs FP64)",
@@ -445,21 +543,29 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": w["text"], "lattice": "x".join(map(str, dims)), "nrhs": nrhs,
+        "data": "synthetic (seeded random SU(3) links, Gaussian right-hand sides)",
+        "config": {"workload": w["text"] + ("; the FP64 GPU path (FP64 smoother) timed alongside"
+                                            if args.fp64_steps > 0 else ""),
+                   "lattice": "x".join(map(str, dims)), "nrhs": nrhs,
                    "smoother": w["sap"], "parallelism": "single GPU", "link_compression": compressed,
                    **({"sap_half_fields": True} if args.sap_half_fields else {})},
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "roofline": roof,
         "roofline_dslash": {"bound": "hbm", "kernel": main_cls, "achieved": rd["gbs"], "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": rd["frac_hbm"], "traffic": traffic.get(main_cls),
+                            "unit": "GB/s", "frac": rd["frac_hbm"], "frac_of_copy": round(rd["gbs"] / copy_gbs, 4),
+                            "traffic": traffic.get(main_cls),
                             "avg_ms": rd["avg_ms"], "bytes_per_launch": rd["bytes_per_launch"],
                             # with gauge compression the kernel reads 48 of the 72 link reals per site
                             # that the algorithmic figure counts
                             "format_bytes_per_launch": rd["bytes_per_launch"] - (24 * 8 * V if compressed else 0)},
         "dslash_frac_hbm": round(dslash_gbs / HBM_PEAK_GBS, 4),
         "dslash_standalone": standalone,
-        "time_to_solution_s": {"mixed": round(t_mixed, 4), "fp64": None if t64 is None else round(t64, 4),
-                               "fp64_over_mixed": None if t64 is None else round(t64 / t_mixed, 3)},
+        "time_to_solution_s": {"mixed": round(float(np.median(tsteps)), 4), "mixed_min": round(min(tsteps), 4),
+                               "mixed_repeats": len(tsteps),
+                               "fp64": None if t64 is None else round(t64, 4),
+                               "fp64_min": None if t64 is None else round(min(t64s), 4),
+                               "fp64_repeats": len(t64s),
+                               "fp64_over_mixed": None if t64 is None else round(t64 / float(np.median(tsteps)), 3)},
         "multi_rhs": None if sequential is None else {
             "nrhs": nrhs, "fused_s": round(t_mixed, 4), "one_at_a_time_s": round(sequential, 4),
             "speedup": round(sequential / t_mixed, 3)},
