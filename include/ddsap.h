@@ -217,6 +217,25 @@ dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int 
 dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr,
                     int prec, int nrhs);
 
+/* dd_sap for callers that cannot allocate device memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * computes exactly what dd_sap computes (same kernels, same arguments,
+ * layout and errors) but allocates nothing: the smoother's scratch (the face
+ * buffers that pass boundary half spinors between the colours and the block
+ * residual carried between visits, 2 * dd_spinor_bytes(ctx, prec, nrhs)
+ * bytes) lives in a fixed device array of DD_SAP_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends, and
+ * ncy = 0 clears psi with a kernel.  The caller still passes eta and psi.
+ * DD_INVALID_ARG (with a message) if the scratch would exceed the array
+ * (e.g. FP32, one right-hand side: up to 663,552 sites = 24^3 x 48).  All
+ * calls on one GPU share that GPU's array, whose contents persist between
+ * calls (nothing in it needs to start at zero): calls that overlap on one
+ * GPU -- from different streams or host threads -- race, so the caller must
+ * order them.  No profiler events are recorded for it. */
+#define DD_SAP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+dd_status dd_sap_noalloc(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr, int prec,
+                         int nrhs);
+
 /* Solve D x_r = b_r (r < nrhs) with FGMRES(m) preconditioned by SAP in
  * params->sap_prec, the Arnoldi basis, orthogonalisation, true residuals and
  * reductions in FP64 on the device.  b, x: canonical FP64 spinors (device

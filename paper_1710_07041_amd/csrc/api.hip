@@ -133,6 +133,17 @@ dd_status dd_create(const int dims[4], const int block[4], const int bcs[4], voi
         delete ctx;
         return DD_HIP_ERROR;
     }
+    {
+        // the device address of dd_sap_noalloc's fixed scratch array, looked
+        // up once per device while that device is current
+        void *scr = nullptr;
+        dd::Status s = dd::noalloc_scratch(ctx->device, &scr);
+        if (!s.good()) {
+            g_create_error = "dd_create: " + s.msg;
+            delete ctx;
+            return s.code;
+        }
+    }
     // colour lists in canonical block order: the sweep kernels map contiguous
     // ranges of these lists onto one XCD each
     std::vector<int> lists[2];
@@ -319,6 +330,21 @@ dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, i
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
         return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec, nullptr, true);
+    });
+}
+
+dd_status dd_sap_noalloc(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int ncy, int nmr, int prec,
+                         int nrhs)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!m0 || !eta || !psi || eta == psi || !prec_ok(prec) || nrhs < 1 || nrhs > DD_MAX_RHS || ncy < 0 || nmr < 0)
+        return fail(ctx, DD_INVALID_ARG, "dd_sap_noalloc: bad argument");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_sap_noalloc: no gauge field");
+    for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap_noalloc: non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::run_sap_noalloc(ctx, m0, nrhs, eta, psi, ncy, nmr, prec);
     });
 }
 

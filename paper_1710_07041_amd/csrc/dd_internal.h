@@ -105,7 +105,8 @@ struct ProfScope {
     int cls;
     double bytes, flops;
     hipEvent_t a = nullptr;
-    ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl);
+    // enable = false: no events are recorded (and none created)
+    ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl, bool enable = true);
     ~ProfScope();
 };
 
@@ -176,6 +177,7 @@ struct SapSlots {
     // the sweeps' scratch (face buffers and the carried block residual,
     // sap_scratch_bytes), owned by the caller; must be set with per-slot data
     void *scratch = nullptr;
+    bool quiet = false; // no profiler events (the no-allocation path)
 };
 size_t sap_scratch_bytes(const GeomHost &g, int prec, int nrhs);
 // grows the context's scratch (used when no SapSlots::scratch is given)
@@ -183,6 +185,13 @@ Status reserve_sap_scratch(dd_ctx *ctx, int prec, int nrhs);
 // eo selects the even-odd preconditioned block solve
 Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr, int prec,
                const SapSlots *slots = nullptr, bool eo = false);
+
+// noalloc.hip (the fixed array holds DD_SAP_NOALLOC_SCRATCH_BYTES, ddsap.h)
+// Device address of `device`'s fixed scratch array (looked up once per device).
+Status noalloc_scratch(int device, void **out);
+// dd_sap with the scratch in the fixed array: no device memory is allocated.
+Status run_sap_noalloc(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr,
+                       int prec);
 
 // engine.hip
 Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,

@@ -60,8 +60,8 @@ void Prof::reset()
     }
 }
 
-ProfScope::ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl)
-    : p(pr.on ? &pr : nullptr), st(s), cls(c), bytes(by), flops(fl)
+ProfScope::ProfScope(Prof &pr, hipStream_t s, int c, double by, double fl, bool enable)
+    : p(pr.on && enable ? &pr : nullptr), st(s), cls(c), bytes(by), flops(fl)
 {
     if (!p) return;
     a = p->get();

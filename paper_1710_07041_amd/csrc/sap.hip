@@ -602,7 +602,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
 }
 
 template <typename S, typename A, typename RES, bool EO, typename SF = S>
-Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces, void *resid)
+Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, void *faces, void *resid, bool quiet)
 {
     // algorithmic traffic of one colour sweep: links + clover once, eta (or
     // the carried residual), psi (read only when nonzero), psi written and,
@@ -620,7 +620,7 @@ Status sweep(dd_ctx *ctx, const SArgs &a, int prec, const void *eta, void *psi, 
     const double fl = sites * n * (a.nmr * 2184.0 + (!CARRY && a.mode == 2 ? 1848.0 : 0.0) + (EO ? 1848.0 : 0.0));
     const int cls = EO ? (prec == DD_F64 ? K_SAP_EO_F64 : prec == DD_F32 ? K_SAP_EO_F32 : K_SAP_EO_F16)
                        : (prec == DD_F64 ? K_SAP_F64 : prec == DD_F32 ? K_SAP_F32 : K_SAP_F16);
-    ProfScope ps(ctx->prof, ctx->stream, cls, by, fl);
+    ProfScope ps(ctx->prof, ctx->stream, cls, by, fl, !quiet);
     if constexpr (EO)
         k_sap_sweep_eo<S, A, RES><<<a.nblk, BS, 0, ctx->stream>>>(
             static_cast<const vec2_t<S> *>(eta), static_cast<vec2_t<S> *>(psi),
@@ -703,6 +703,7 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
     if (!scratch) return Status{DD_INVALID_ARG, "SAP: no scratch buffer"};
     void *faces = scratch;
     void *resid = static_cast<char *>(scratch) + spinor_bytes(ctx->g, prec, nrhs);
+    const bool quiet = slots && slots->quiet;
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;
@@ -712,15 +713,15 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
             a.publish = !(cy == ncy - 1 && col == 1);
             a.write_r = cy < ncy - 1;
             if (eo) {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
-                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResEO, true>(ctx, a, prec, eta, psi, faces, resid, quiet)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid, quiet)));
+                else DD_TRY((sweep<__half, float, ResEO, true>(ctx, a, prec, eta, psi, faces, resid, quiet)));
             } else {
-                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces, resid)));
+                if (prec == DD_F64) DD_TRY((sweep<double, double, ResF64, false>(ctx, a, prec, eta, psi, faces, resid, quiet)));
                 else if (prec == DD_F32 && half_fields)
-                    DD_TRY((sweep<float, float, ResF32, false, __half>(ctx, a, prec, eta, psi, faces, resid)));
-                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces, resid)));
-                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces, resid)));
+                    DD_TRY((sweep<float, float, ResF32, false, __half>(ctx, a, prec, eta, psi, faces, resid, quiet)));
+                else if (prec == DD_F32) DD_TRY((sweep<float, float, ResF32, false>(ctx, a, prec, eta, psi, faces, resid, quiet)));
+                else DD_TRY((sweep<__half, float, ResF16, false>(ctx, a, prec, eta, psi, faces, resid, quiet)));
             }
         }
     return Status::ok();

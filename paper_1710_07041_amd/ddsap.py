@@ -38,7 +38,7 @@ DD_MAX_RHS = 16
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_sap_half_fields", "dd_sap_half_fields", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
-    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_solve", "dd_debug_poison_half_smoother", "dd_profile_enable",
+    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_sap_noalloc", "dd_solve", "dd_debug_poison_half_smoother", "dd_profile_enable",
     "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
@@ -98,6 +98,7 @@ _sigs = {
     "dd_apply_D_block": ([_vp, _d, _l, _vp, _vp, _i], _i),
     "dd_sap": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_sap_eo": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
+    "dd_sap_noalloc": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
     "dd_debug_poison_half_smoother": ([_vp, _i], _i),
     "dd_profile_enable": ([_vp, _i], _i),
@@ -245,6 +246,19 @@ class Context:
         fn = _lib.dd_sap_eo if eo else _lib.dd_sap
         self._check(fn(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), int(ncy), int(nmr), PREC.get(prec, prec),
                        int(nrhs)))
+
+    def sap_noalloc(self, m0, eta, psi, ncy, nmr, prec, nrhs=1, raise_on_fail=True):
+        """dd_sap_noalloc: dd_sap with its scratch in the library's fixed device
+        array (no allocation).  Returns the status when raise_on_fail is off."""
+        _, mp = _masses(m0, nrhs)
+        st = _lib.dd_sap_noalloc(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), int(ncy), int(nmr),
+                                 PREC.get(prec, prec), int(nrhs))
+        if raise_on_fail:
+            self._check(st)
+        return st
+
+    def last_error(self) -> str:
+        return _lib.dd_last_error(self._h).decode()
 
     def solve(self, m0, b, x, nrhs=1, params: dd_params | None = None, raise_on_fail=True):
         """b, x: canonical complex128 device tensors (nrhs, V, 4, 3); x holds x0."""
