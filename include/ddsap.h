@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define DD_ABI_VERSION 5
+#define DD_ABI_VERSION 6
 #define DD_MAX_RHS 16 /* right-hand sides fused into one launch */
 
 typedef enum {
@@ -93,6 +93,9 @@ typedef struct {
     int nmr;          /* MR steps per block and sweep (4)                        */
     int sap_prec;     /* dd_prec of the smoother (DD_F32)                        */
     int sap_eo;       /* 1: even-odd preconditioned block solves (dd_sap_eo), 0 */
+    int amg;          /* 1: precondition with the two-grid method of dd_amg_setup
+                         (coarse correction + SAP post-smoothing in sap_prec,
+                         DD_F32 or DD_F64; ncy/nmr/sap_eo are then unused), 0  */
 } dd_params;
 
 /* Per right-hand-side result of dd_solve. */
@@ -245,6 +248,87 @@ dd_status dd_sap_noalloc(dd_ctx *ctx, const double *m0, const void *eta, void *p
  * every right-hand side converged, else the first failing status. */
 dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs,
                    const dd_params *params, dd_solve_info *info);
+
+/* ---------------------------------------------------------------------------
+ * Two-level coarse correction (the multigrid level of DD-alpha-AMG)
+ * ---------------------------------------------------------------------------
+ * The paper's solver is DD-alpha-AMG (Sec. 1): a multigrid method whose
+ * fine-grid smoother is the Schwarz method above (Sec. 2.1) and which has a
+ * coarse grid (Sec. 5).  The two-level form here follows the published
+ * method (Frommer, Kahl, Krieg, Leder, Rottmann, SIAM J. Sci. Comput. 36
+ * (2014) A1581):
+ *   aggregates    the 4^4 Schwarz blocks, each split into its chiral halves
+ *                 (spins 0-1 and spins 2-3), so P commutes with gamma_5;
+ *   test vectors  from the caller's starting vectors by inverse iteration
+ *                 with SAP (v <- SAP(v)/|SAP(v)|, setup_iters times), then
+ *                 `adapt` rounds with the two-grid method in SAP's place;
+ *   P             the test vectors restricted to each aggregate and
+ *                 orthonormalised there by Gram-Schmidt in their order;
+ *   D_c           P^+ D P: 2 nvec unknowns per block, a nearest-neighbour
+ *                 operator on the lattice of blocks, built at m0 = 0 (the
+ *                 mass enters as + m0 since P^+ P = 1, so one setup serves
+ *                 every mass; the test vectors are tuned to the setup mass);
+ *   coarse solve  coarse_k steps of GMRES from zero (the least-residual
+ *                 vector of the Krylov space), on the device, FP64 vectors
+ *                 and an FP32 copy of D_c;
+ *   two-grid B    psi_0 = P x_c with x_c the coarse solve of
+ *                 D_c x_c = P^+ eta, then psi = psi_0 + SAP(eta - D psi_0)
+ *                 with post_ncy cycles of post_nmr MR steps.
+ * Layouts: P (dd_amg_interpolation) [block][c][i][component][site], complex,
+ * component = (spin - 2c) * 3 + colour, site = the block-local index
+ * x + 4y + 16z + 64t; D_c (dd_amg_coarse_operator) [block][d][k'][k],
+ * complex, d = 0 the block, 1 + 2 mu its +mu neighbour, 2 + 2 mu its -mu
+ * neighbour, entry (row k, column k') with k = c * nvec + i; coarse vectors
+ * [rhs][block][k] complex FP64 (device).  A context holds one setup; a new
+ * dd_amg_setup replaces it. */
+typedef struct {
+    int nvec;        /* test vectors, 1..16 (8): 2 nvec coarse unknowns per block */
+    int setup_iters; /* inverse-iteration steps per test vector (3)               */
+    int setup_ncy;   /* SAP cycles per setup step (4)                               */
+    int setup_nmr;   /* MR steps per block in them (4)                              */
+    int setup_prec;  /* precision of the setup's smoother, DD_F32 or DD_F64 (F32)   */
+    int adapt;       /* adaptive rounds with the two-grid method (1)                */
+    int coarse_k;    /* GMRES steps of the coarse solve, 1..32 (16)                 */
+    int post_ncy;    /* SAP cycles after the coarse correction, >= 0 (4)            */
+    int post_nmr;    /* MR steps per block in them (4)                              */
+} dd_amg_params;
+
+/* Fill *p with the defaults shown above. */
+void dd_amg_default_params(dd_amg_params *p);
+
+/* Set up the coarse level on ctx's gauge field.  v0: nvec starting vectors,
+ * canonical FP64 (device, nvec * 24 * V doubles), e.g. Gaussian; m0: the
+ * mass the test vectors are tuned to.  Synchronises.  DD_NO_FIELD,
+ * DD_INVALID_ARG (parameters out of range), DD_NAN (non-finite v0), DD_OOM. */
+dd_status dd_amg_setup(dd_ctx *ctx, double m0, const double *v0, const dd_amg_params *p);
+
+/* Complex entries of one coarse vector (nblocks * 2 nvec), 0 without a setup. */
+size_t dd_amg_coarse_size(const dd_ctx *ctx);
+
+/* Copy the FP64 interpolation / coarse operator to host memory in the
+ * layouts above (P: nblocks*2*nvec*6*256 complex; D_c: nblocks*9*(2 nvec)^2
+ * complex).  Synchronises.  DD_INVALID_ARG without a setup. */
+dd_status dd_amg_interpolation(dd_ctx *ctx, double *P_host);
+dd_status dd_amg_coarse_operator(dd_ctx *ctx, double *Dc_host);
+
+/* xc = P^+ x (restriction) and x = P xc (prolongation) for nrhs right-hand
+ * sides: x a blocked spinor buffer of precision prec (DD_F64: FP64
+ * interpolation and arithmetic; DD_F32: the FP32 copy and FP32 arithmetic),
+ * xc coarse vectors (device, FP64). */
+dd_status dd_amg_restrict(dd_ctx *ctx, const void *x, double *xc, int prec, int nrhs);
+dd_status dd_amg_prolong(dd_ctx *ctx, const double *xc, void *x, int prec, int nrhs);
+
+/* yc = (D_c + m0[r]) xc for each right-hand side r (m0: host, nrhs values). */
+dd_status dd_amg_coarse_apply(dd_ctx *ctx, const double *m0, const double *xc, double *yc, int nrhs);
+
+/* xc = k steps of GMRES from zero on (D_c + m0[r]) xc = bc (1 <= k <= 32;
+ * the Krylov space may close earlier, then xc solves exactly). */
+dd_status dd_amg_coarse_solve(dd_ctx *ctx, const double *m0, const double *bc, double *xc, int k, int nrhs);
+
+/* psi = B eta, the two-grid preconditioner, for nrhs right-hand sides of
+ * precision prec (DD_F64 or DD_F32 blocked buffers; eta and psi must not
+ * overlap). */
+dd_status dd_amg_precondition(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int prec, int nrhs);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of solves over resident gauge fields

@@ -72,6 +72,21 @@ void dd_default_params(dd_params *p)
     p->nmr = 4;
     p->sap_prec = DD_F32;
     p->sap_eo = 0;
+    p->amg = 0;
+}
+
+void dd_amg_default_params(dd_amg_params *p)
+{
+    if (!p) return;
+    p->nvec = 8;
+    p->setup_iters = 3;
+    p->setup_ncy = 4;
+    p->setup_nmr = 4;
+    p->setup_prec = DD_F32;
+    p->adapt = 1;
+    p->coarse_k = 16;
+    p->post_ncy = 4;
+    p->post_nmr = 4;
 }
 
 const char *dd_last_error(const dd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
@@ -359,6 +374,9 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
         return fail(ctx, DD_INVALID_ARG, "dd_solve: bad argument");
     if (p.m < 1 || p.m > 32 || !(p.tol > 0) || p.max_restarts < 0 || p.ncy < 0 || p.nmr < 0 || !prec_ok(p.sap_prec))
         return fail(ctx, DD_INVALID_ARG, "dd_solve: bad parameters (1 <= m <= 32, tol > 0, ...)");
+    if (p.amg && !ctx->amg) return fail(ctx, DD_INVALID_ARG, "dd_solve: amg = 1 needs dd_amg_setup first");
+    if (p.amg && p.sap_prec == DD_F16)
+        return fail(ctx, DD_INVALID_ARG, "dd_solve: the two-grid preconditioner smooths in FP32 or FP64");
     if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_solve: no gauge field");
     for (int r = 0; r < nrhs; ++r)
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_solve: non-finite mass");
@@ -366,6 +384,88 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
         DD_TRY(set_device(ctx));
         return dd::solve(ctx, m0, b, x, nrhs, p, info);
     });
+}
+
+dd_status dd_amg_setup(dd_ctx *ctx, double m0, const double *v0, const dd_amg_params *p)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!v0 || !p || !std::isfinite(m0)) return fail(ctx, DD_INVALID_ARG, "dd_amg_setup: bad argument");
+    if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_amg_setup: no gauge field");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        ctx->engine.reset(); // an engine's two-grid workspace belongs to the previous setup
+        dd::Status s = dd::amg_setup(ctx, m0, v0, *p);
+        if (!s.good()) ctx->amg.reset();
+        return s;
+    });
+}
+
+size_t dd_amg_coarse_size(const dd_ctx *ctx) { return ctx ? dd::amg_coarse_size(ctx) : 0; }
+
+dd_status dd_amg_interpolation(dd_ctx *ctx, double *P_host)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!P_host || !ctx->amg) return fail(ctx, DD_INVALID_ARG, "dd_amg_interpolation: no setup or null pointer");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return dd::amg_export(ctx, P_host, nullptr);
+    });
+}
+
+dd_status dd_amg_coarse_operator(dd_ctx *ctx, double *Dc_host)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!Dc_host || !ctx->amg) return fail(ctx, DD_INVALID_ARG, "dd_amg_coarse_operator: no setup or null pointer");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        DD_HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return dd::amg_export(ctx, nullptr, Dc_host);
+    });
+}
+
+namespace {
+dd_status amg_call(dd_ctx *ctx, const char *name, int op, const double *m0, int nrhs, const void *in, void *out,
+                   int prec, int k)
+{
+    if (!ctx) return DD_INVALID_ARG;
+    if (!in || !out || in == out || nrhs < 1 || nrhs > DD_MAX_RHS || (prec != DD_F64 && prec != DD_F32) ||
+        ((op >= 2) && !m0))
+        return fail(ctx, DD_INVALID_ARG, std::string(name) + ": bad argument");
+    if (!ctx->amg) return fail(ctx, DD_INVALID_ARG, std::string(name) + ": call dd_amg_setup first");
+    if (m0)
+        for (int r = 0; r < nrhs; ++r)
+            if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, std::string(name) + ": non-finite mass");
+    return guarded(ctx, [&]() -> dd::Status {
+        DD_TRY(set_device(ctx));
+        return dd::amg_standalone(ctx, op, m0, nrhs, in, out, prec, k);
+    });
+}
+} // namespace
+
+dd_status dd_amg_restrict(dd_ctx *ctx, const void *x, double *xc, int prec, int nrhs)
+{
+    return amg_call(ctx, "dd_amg_restrict", 0, nullptr, nrhs, x, xc, prec, 0);
+}
+
+dd_status dd_amg_prolong(dd_ctx *ctx, const double *xc, void *x, int prec, int nrhs)
+{
+    return amg_call(ctx, "dd_amg_prolong", 1, nullptr, nrhs, xc, x, prec, 0);
+}
+
+dd_status dd_amg_coarse_apply(dd_ctx *ctx, const double *m0, const double *xc, double *yc, int nrhs)
+{
+    return amg_call(ctx, "dd_amg_coarse_apply", 2, m0, nrhs, xc, yc, DD_F64, 0);
+}
+
+dd_status dd_amg_coarse_solve(dd_ctx *ctx, const double *m0, const double *bc, double *xc, int k, int nrhs)
+{
+    return amg_call(ctx, "dd_amg_coarse_solve", 3, m0, nrhs, bc, xc, DD_F64, k);
+}
+
+dd_status dd_amg_precondition(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int prec, int nrhs)
+{
+    return amg_call(ctx, "dd_amg_precondition", 4, m0, nrhs, eta, psi, prec, 0);
 }
 
 dd_status dd_debug_poison_half_smoother(dd_ctx *ctx, int count)

@@ -77,6 +77,7 @@ enum KClass {
     K_DSLASH_F64 = 0, K_DSLASH_F32IN_F64, K_DSLASH_F32, K_DSLASH_F16, K_DSLASH_BLOCK,
     K_SAP_F64, K_SAP_F32, K_SAP_F16, K_SAP_EO_F64, K_SAP_EO_F32, K_SAP_EO_F16,
     K_CGS_DOTS, K_CGS_UPDATE, K_CGS_NORMALIZE, K_REDUCE, K_COMBINE, K_CONVERT, K_PACK,
+    K_AMG_RESTRICT, K_AMG_COARSE, K_AMG_PROLONG,
     K_NCLASS
 };
 const char *kclass_name(int k);
@@ -114,6 +115,14 @@ class Engine; // engine.hip
 struct EngineDeleter {
     void operator()(Engine *e) const; // engine.hip
 };
+struct AmgData; // coarse.hip: interpolation, coarse operator, workspace
+struct AmgDeleter {
+    void operator()(AmgData *a) const;
+};
+struct AmgWork; // coarse.hip: the two-grid preconditioner's workspace for W slots
+struct AmgWorkDeleter {
+    void operator()(AmgWork *w) const;
+};
 
 } // namespace dd
 
@@ -135,6 +144,7 @@ struct dd_ctx {
     dd::DevBuf sap_scratch; // face buffers and carried residual of the Schwarz sweeps of dd_sap
     dd::Prof prof;
     std::unique_ptr<dd::Engine, dd::EngineDeleter> engine; // reused by dd_solve
+    std::unique_ptr<dd::AmgData, dd::AmgDeleter> amg;      // coarse level of dd_amg_setup
 };
 
 namespace dd {
@@ -155,8 +165,9 @@ Status unpack_slot(dd_ctx *ctx, hipStream_t st, const void *blocked, double *can
 Status any_nonfinite(dd_ctx *ctx, const double *p, size_t n, bool &bad);
 
 // dslash.hip
-// out = D in (resid == nullptr) or out = resid - D in.  in_prec may differ
-// from out_prec only for (F32 in, F64 out) and (F64 in, F64 out).  Masses
+// out = D in (resid == nullptr) or out = resid - D in (the residual form:
+// FP64 or FP32 throughout).  in_prec may differ from out_prec only for
+// (F32 in, F64 out) and (F64 in, F64 out).  Masses
 // come from the host array m0 or, when m0_dev is set, from device memory;
 // in_off (device, nullable) adds a per-rhs element offset to the input.
 // active (device, nullable): right-hand sides with active[r] == 0 are skipped
@@ -192,6 +203,22 @@ Status noalloc_scratch(int device, void **out);
 // dd_sap with the scratch in the fixed array: no device memory is allocated.
 Status run_sap_noalloc(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *psi, int ncy, int nmr,
                        int prec);
+
+// coarse.hip
+Status amg_setup(dd_ctx *ctx, double m0, const double *v0, const dd_amg_params &p);
+// P and D_c (FP64) to host memory (either may be null)
+Status amg_export(dd_ctx *ctx, double *P_host, double *A_host);
+size_t amg_coarse_size(const dd_ctx *ctx);
+// op: 0 restrict, 1 prolong, 2 coarse apply, 3 coarse solve (k steps), 4 two-grid
+Status amg_standalone(dd_ctx *ctx, int op, const double *m0, int nrhs, const void *in, void *out, int prec, int k);
+AmgWork *amg_work_new();
+// sizes the workspace for W slots of precision prec and a coarse basis of
+// max(kmax, the setup's coarse_k) + 1 vectors
+Status amg_reserve(dd_ctx *ctx, AmgWork &wk, int W, int prec, int kmax);
+// z = B eta for W slots (slot r of eta at eta + eta_off[r], of z at z +
+// z_off[r], in the blocked layout with W right-hand sides; offsets nullable)
+Status run_two_grid(dd_ctx *ctx, AmgWork &wk, int W, const void *eta, const long *eta_off, int prec, void *z,
+                    const long *z_off, const double *m0_dev, const int *active);
 
 // engine.hip
 Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,

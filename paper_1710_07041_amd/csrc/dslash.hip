@@ -469,8 +469,9 @@ Status launch_dslash(dd_ctx *ctx, const double *m0, int nrhs, const void *in, in
                   : launch<double, double, double, double, false>(ctx, a, in, out, DD_F64, resid);
     if (in_prec == DD_F32 && out_prec == DD_F64 && field_prec == DD_F64 && !rs)
         return launch<float, double, double, double, false>(ctx, a, in, out, DD_F64, nullptr);
-    if (in_prec == DD_F32 && out_prec == DD_F32 && field_prec == DD_F32 && !rs)
-        return launch<float, float, float, float, false>(ctx, a, in, out, DD_F32, nullptr);
+    if (in_prec == DD_F32 && out_prec == DD_F32 && field_prec == DD_F32)
+        return rs ? launch<float, float, float, float, true>(ctx, a, in, out, DD_F32, resid)
+                  : launch<float, float, float, float, false>(ctx, a, in, out, DD_F32, nullptr);
     if (in_prec == DD_F16 && out_prec == DD_F16 && field_prec == DD_F16 && !rs)
         return launch<__half, __half, __half, float, false>(ctx, a, in, out, DD_F16, nullptr);
     return Status{DD_INVALID_ARG, "unsupported precision combination for the operator"};

@@ -22,6 +22,7 @@ struct EngineParams {
     double tol = 1e-10;
     int max_restarts = 100;
     bool graphs = false; // capture the Arnoldi step as hipGraphs (needs a non-null stream)
+    bool amg = false;    // precondition with the two-grid method of dd_amg_setup (FP32/FP64 smoother)
 };
 
 enum SlotStateKind { SLOT_FREE = 0, SLOT_RESTART = 1, SLOT_CYCLE = 2, SLOT_DONE = 3 };
@@ -76,6 +77,8 @@ class Engine {
     SlotState &slot(int r);
     dd_ctx *ctx() const;
     static size_t bytes_per_slot(const GeomHost &g, int m, int sap_prec);
+    // (re)size the two-grid preconditioner's workspace for the context's setup
+    Status prepare_amg();
 
   private:
     struct Impl;

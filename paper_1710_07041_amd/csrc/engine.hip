@@ -520,6 +520,7 @@ struct Engine::Impl {
     long vlen = 0; // complex entries of one width-wide vector
     int G = 0;
     DevBuf V, Z, w, xb, bb, lp, sapout, sapscr, partial, res, res2, resb, y, scl, slots;
+    std::unique_ptr<AmgWork, AmgWorkDeleter> amgw; // the two-grid preconditioner's workspace
     SlotArrays *h_slots[3] = {nullptr, nullptr, nullptr}; // ring of pinned staging buffers
     int ring = 0;
     double2 *h_res = nullptr, *h_resb = nullptr, *h_y = nullptr;
@@ -680,7 +681,13 @@ struct Engine::Impl {
         ss.m0_dev = d_m0();
         ss.active = d_active(); // done or empty slots cost no smoother work
         ss.scratch = sapscr.p;
-        if (P.ncy == 0) {
+        if (P.amg) {
+            // two-grid preconditioner: coarse correction, then post-smoothing
+            if (sap_prec == DD_F64)
+                DD_TRY(run_two_grid(ctx, *amgw, W, V.p, d_eta_off(), DD_F64, Z.p, d_psi_off(), d_m0(), d_active()));
+            else
+                DD_TRY(run_two_grid(ctx, *amgw, W, lp.p, nullptr, DD_F32, Z.p, d_psi_off(), d_m0(), d_active()));
+        } else if (P.ncy == 0) {
             // no smoother: z_j = v_j (the smoother-precision copy, or V itself in FP64)
             ProfScope ps(ctx->prof, st(), K_CONVERT, (double)vlen * 2 * 2 * real_bytes(zprec), 0.0);
             if (sap_prec == DD_F64)
@@ -775,6 +782,15 @@ size_t Engine::bytes_per_slot(const GeomHost &g, int m, int sap_prec)
 
 int Engine::width() const { return d->W; }
 const EngineParams &Engine::params() const { return d->P; }
+
+Status Engine::prepare_amg()
+{
+    Impl &e = *d;
+    if (!e.ctx->amg) return Status{DD_INVALID_ARG, "the two-grid preconditioner needs dd_amg_setup first"};
+    if (e.P.sap_prec == DD_F16) return Status{DD_INVALID_ARG, "the two-grid preconditioner smooths in FP32 or FP64"};
+    if (!e.amgw) e.amgw.reset(amg_work_new());
+    return amg_reserve(e.ctx, *e.amgw, e.W, e.zprec, 0);
+}
 SlotState &Engine::slot(int r) { return d->S[r]; }
 dd_ctx *Engine::ctx() const { return d->ctx; }
 
@@ -807,6 +823,7 @@ Status Engine::init(dd_ctx *ctx, const EngineParams &p)
     DD_TRY(e.y.alloc((size_t)e.W * ENGINE_MAXM * 16));
     DD_TRY(e.scl.alloc((size_t)e.W * 8));
     DD_TRY(e.slots.alloc(sizeof(SlotArrays)));
+    if (p.amg) DD_TRY(prepare_amg());
     for (auto &hs : e.h_slots) {
         DD_HIP_TRY(hipHostMalloc((void **)&hs, sizeof(SlotArrays), hipHostMallocDefault));
         std::memset(hs, 0, sizeof(SlotArrays));
@@ -1163,8 +1180,10 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
     ep.max_restarts = p.max_restarts;
     ep.graphs = false;
     // reuse the context's engine when the shape matches
+    ep.amg = p.amg != 0;
     Engine *eng = ctx->engine.get();
-    if (!eng || eng->width() != nrhs || eng->params().m != p.m || eng->params().sap_prec != p.sap_prec) {
+    if (!eng || eng->width() != nrhs || eng->params().m != p.m || eng->params().sap_prec != p.sap_prec ||
+        eng->params().amg != ep.amg) {
         ctx->engine.reset();
         std::unique_ptr<Engine, EngineDeleter> ne(new Engine());
         DD_TRY(ne->init(ctx, ep));
@@ -1173,6 +1192,7 @@ Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs
     } else {
         eng->set_params(ep);
     }
+    if (ep.amg) DD_TRY(eng->prepare_amg()); // sizes follow the latest dd_amg_setup
     const size_t vstride = (size_t)ctx->g.V * 12 * 2; // doubles per canonical rhs
     for (int r = 0; r < nrhs; ++r) DD_TRY(eng->admit(r, b + r * vstride, x + r * vstride, m0[r], 0, r));
     for (int guard = 0; eng->busy_slots() > 0; ++guard) {

@@ -10,6 +10,7 @@ const char *kclass_name(int k)
         "dslash_f64", "dslash_f32in_f64", "dslash_f32", "dslash_f16", "dslash_block",
         "sap_sweep_f64", "sap_sweep_f32", "sap_sweep_f16", "sap_sweep_eo_f64", "sap_sweep_eo_f32", "sap_sweep_eo_f16",
         "cgs_dots", "cgs_update", "restart_norm", "reduce", "combine", "convert", "pack",
+        "amg_restrict", "amg_coarse_solve", "amg_prolong",
     };
     return (k >= 0 && k < K_NCLASS) ? names[k] : "?";
 }

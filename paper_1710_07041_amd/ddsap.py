@@ -38,7 +38,9 @@ DD_MAX_RHS = 16
 EXPORTS = [
     "dd_abi_version", "dd_default_params", "dd_create", "dd_destroy", "dd_last_error", "dd_synchronize",
     "dd_set_gauge", "dd_set_link_compression", "dd_link_compression", "dd_set_sap_half_fields", "dd_sap_half_fields", "dd_set_clover", "dd_spinor_bytes", "dd_pack_spinor", "dd_unpack_spinor", "dd_apply_D",
-    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_sap_noalloc", "dd_solve", "dd_debug_poison_half_smoother", "dd_profile_enable",
+    "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_sap_noalloc", "dd_solve", "dd_amg_default_params",
+    "dd_amg_setup", "dd_amg_coarse_size", "dd_amg_interpolation", "dd_amg_coarse_operator", "dd_amg_restrict",
+    "dd_amg_prolong", "dd_amg_coarse_apply", "dd_amg_coarse_solve", "dd_amg_precondition", "dd_debug_poison_half_smoother", "dd_profile_enable",
     "dd_profile_read",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
@@ -48,7 +50,14 @@ EXPORTS = [
 
 class dd_params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
-                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("sap_eo", ctypes.c_int)]
+                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int), ("sap_eo", ctypes.c_int),
+                ("amg", ctypes.c_int)]
+
+
+class dd_amg_params(ctypes.Structure):
+    _fields_ = [("nvec", ctypes.c_int), ("setup_iters", ctypes.c_int), ("setup_ncy", ctypes.c_int),
+                ("setup_nmr", ctypes.c_int), ("setup_prec", ctypes.c_int), ("adapt", ctypes.c_int),
+                ("coarse_k", ctypes.c_int), ("post_ncy", ctypes.c_int), ("post_nmr", ctypes.c_int)]
 
 
 class dd_solve_info(ctypes.Structure):
@@ -101,6 +110,16 @@ _sigs = {
     "dd_sap_noalloc": ([_vp, _dp, _vp, _vp, _i, _i, _i, _i], _i),
     "dd_solve": ([_vp, _dp, _vp, _vp, _i, ctypes.POINTER(dd_params), ctypes.POINTER(dd_solve_info)], _i),
     "dd_debug_poison_half_smoother": ([_vp, _i], _i),
+    "dd_amg_default_params": ([ctypes.POINTER(dd_amg_params)], None),
+    "dd_amg_setup": ([_vp, _d, _vp, ctypes.POINTER(dd_amg_params)], _i),
+    "dd_amg_coarse_size": ([_vp], ctypes.c_size_t),
+    "dd_amg_interpolation": ([_vp, _vp], _i),
+    "dd_amg_coarse_operator": ([_vp, _vp], _i),
+    "dd_amg_restrict": ([_vp, _vp, _vp, _i, _i], _i),
+    "dd_amg_prolong": ([_vp, _vp, _vp, _i, _i], _i),
+    "dd_amg_coarse_apply": ([_vp, _dp, _vp, _vp, _i], _i),
+    "dd_amg_coarse_solve": ([_vp, _dp, _vp, _vp, _i, _i], _i),
+    "dd_amg_precondition": ([_vp, _dp, _vp, _vp, _i, _i], _i),
     "dd_profile_enable": ([_vp, _i], _i),
     "dd_server_default_config": ([ctypes.POINTER(dd_server_config)], None),
     "dd_server_create": ([ctypes.POINTER(dd_server_config), ctypes.POINTER(_vp)], _i),
@@ -271,6 +290,51 @@ class Context:
             raise DDError(st, _lib.dd_last_error(self._h).decode())
         return st, out
 
+    # -- two-level coarse correction --------------------------------------
+    def amg_setup(self, m0, v0, params=None):
+        """v0: canonical complex128 device tensor (nvec, V, 4, 3) of starting vectors."""
+        p = params if params is not None else default_amg_params()
+        self._check(_lib.dd_amg_setup(self._h, float(m0), _vp(_ptr(v0)), ctypes.byref(p)))
+        self._amg_nvec = p.nvec
+
+    def amg_coarse_size(self) -> int:
+        return int(_lib.dd_amg_coarse_size(self._h))
+
+    def amg_interpolation(self):
+        """P as numpy complex128 (nblocks, 2, nvec, 6, 256): [block][chirality][vector][component][site]."""
+        n = self._amg_nvec
+        nb = self.volume // 256
+        out = np.empty((nb, 2, n, 6, 256), dtype=np.complex128)
+        self._check(_lib.dd_amg_interpolation(self._h, _vp(out.ctypes.data)))
+        return out
+
+    def amg_coarse_operator(self):
+        """D_c as numpy complex128 (nblocks, 9, 2 nvec, 2 nvec): [block][d][column k'][row k]."""
+        n2 = 2 * self._amg_nvec
+        nb = self.volume // 256
+        out = np.empty((nb, 9, n2, n2), dtype=np.complex128)
+        self._check(_lib.dd_amg_coarse_operator(self._h, _vp(out.ctypes.data)))
+        return out
+
+    def amg_restrict(self, x, xc, prec, nrhs=1):
+        self._check(_lib.dd_amg_restrict(self._h, _vp(_ptr(x)), _vp(_ptr(xc)), PREC.get(prec, prec), int(nrhs)))
+
+    def amg_prolong(self, xc, x, prec, nrhs=1):
+        self._check(_lib.dd_amg_prolong(self._h, _vp(_ptr(xc)), _vp(_ptr(x)), PREC.get(prec, prec), int(nrhs)))
+
+    def amg_coarse_apply(self, m0, xc, yc, nrhs=1):
+        _, mp = _masses(m0, nrhs)
+        self._check(_lib.dd_amg_coarse_apply(self._h, mp, _vp(_ptr(xc)), _vp(_ptr(yc)), int(nrhs)))
+
+    def amg_coarse_solve(self, m0, bc, xc, k, nrhs=1):
+        _, mp = _masses(m0, nrhs)
+        self._check(_lib.dd_amg_coarse_solve(self._h, mp, _vp(_ptr(bc)), _vp(_ptr(xc)), int(k), int(nrhs)))
+
+    def amg_precondition(self, m0, eta, psi, prec, nrhs=1):
+        _, mp = _masses(m0, nrhs)
+        self._check(_lib.dd_amg_precondition(self._h, mp, _vp(_ptr(eta)), _vp(_ptr(psi)), PREC.get(prec, prec),
+                                             int(nrhs)))
+
     def debug_poison_half_smoother(self, count):
         """Test hook: the next `count` FP16 smoother outputs of solve() (all for
         count < 0) get a non-finite entry, which must trigger the FP32 fallback."""
@@ -287,6 +351,12 @@ class Context:
             raise DDError(DD_HIP_ERROR, _lib.dd_last_error(self._h).decode())
         return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
                                        "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(n)}
+
+
+def default_amg_params() -> dd_amg_params:
+    p = dd_amg_params()
+    _lib.dd_amg_default_params(ctypes.byref(p))
+    return p
 
 
 def default_server_config() -> dd_server_config:

@@ -44,7 +44,7 @@ def test_binding_lists_every_export():
 
 def test_abi_version_and_defaults(lib):
     from paper_1710_07041_amd import ddsap
-    assert ddsap.abi_version() == 5
+    assert ddsap.abi_version() == 6
     p = ddsap.default_params()
     assert (p.m, p.tol, p.max_restarts, p.ncy, p.nmr, p.sap_prec, p.sap_eo) == (20, 1e-10, 100, 12, 4, ddsap.DD_F32, 0)
     c = ddsap.default_server_config()
