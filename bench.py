@@ -4,7 +4,8 @@ SAP-preconditioned FGMRES solve (mixed precision vs FP64) on one MI355X.
 
 Default workload: the 48^3x96 lattice (eps = 0.6, csw = 1, m0 = -0.38), one
 Gaussian right-hand side, the red-black SAP smoother (4^4 blocks, 4 MR steps,
-12 cycles) with FP16 link/clover/spinor storage and FP32 arithmetic inside
+10 cycles: the fastest count of a scan on this lattice) with FP16
+link/clover/spinor storage and FP32 arithmetic inside
 FP64 FGMRES(20), tolerance 1e-10; the FP64 GPU path (the same algorithm with
 an FP64 smoother) is timed alongside.  One step = one complete solve: FP64
 outer iteration (operator, CGS2 orthogonalisation, reductions, true-residual
@@ -52,8 +53,9 @@ WORKLOADS = {
                     "nmr=4 ncy=12, FGMRES(20) FP64, tol 1e-10"),
     "c1": dict(dims=(8, 8, 8, 8), eps=0.3, m0=-0.2, csw=1.0, sap="f32", nrhs=1, source="gaussian",
                text="8^4, eps=0.3, csw=1.0, m0=-0.2, 1 Gaussian RHS, 4^4 blocks, FGMRES(20), tol 1e-10"),
-    "c3": dict(dims=(48, 48, 48, 96), eps=0.6, m0=-0.38, csw=1.0, sap="f16", nrhs=1, source="gaussian",
-               text="48^3x96, eps=0.6, m0=-0.38, SAP FP16 storage / FP32 arithmetic, FGMRES(20) FP64, tol 1e-10"),
+    "c3": dict(dims=(48, 48, 48, 96), eps=0.6, m0=-0.38, csw=1.0, sap="f16", nrhs=1, source="gaussian", ncy=10,
+               text="48^3x96, eps=0.6, m0=-0.38, SAP FP16 storage / FP32 arithmetic, 4^4 blocks nmr=4 ncy=10, "
+                    "FGMRES(20) FP64, tol 1e-10"),
     "c4": dict(dims=(32, 32, 32, 64), eps=0.5, m0=-0.35, csw=1.0, sap="f32", nrhs=12, source="point",
                text="32^3x64, 12 point-source RHS (spin x colour), fused multi-RHS SAP FP32, FGMRES(20) FP64 "
                     "per RHS, tol 1e-10"),
@@ -74,6 +76,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64-smoother solves timed alongside")
     ap.add_argument("--eo-steps", type=int, default=1,
                     help="solves with the even-odd preconditioned smoother (mixed and FP64) timed alongside")
+    ap.add_argument("--amg-steps", type=int, default=2,
+                    help="solves with the two-level preconditioner (coarse correction + SAP post-smoothing, after "
+                         "a separately timed setup) alongside; 0 skips")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="budget of the oracle operator sample")
     ap.add_argument("--cpu-full", action="store_true",
@@ -350,17 +355,19 @@ def main():
     xd = torch.zeros_like(bd)
     m0 = np.full(nrhs, w["m0"])
 
-    def params(sap, eo=False, ncy=None):
+    def params(sap, eo=False, ncy=None, amg=False):
         p = ddsap.default_params()
         p.sap_prec = ddsap.PREC[sap]
         p.sap_eo = int(eo)
-        if ncy is not None:
-            p.ncy = ncy
+        p.amg = int(amg)
+        # SAP cycles per preconditioner call: the count under test in a scan,
+        # else the workload's own (picked by such a scan; library default 12)
+        p.ncy = ncy if ncy is not None else w.get("ncy", p.ncy)
         return p
 
-    def one_solve(sap, eo=False, ncy=None):
+    def one_solve(sap, eo=False, ncy=None, amg=False):
         xd.zero_()
-        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap, eo, ncy), raise_on_fail=False)
+        st, info = ctx.solve(m0, bd, xd, nrhs, params(sap, eo, ncy, amg), raise_on_fail=False)
         if st != ddsap.DD_OK:
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
@@ -439,6 +446,42 @@ def main():
                 "sweep_avg_ms": None if not sweep else round(sweep["total_ms"] / sweep["launches"], 4)}
             log(f"even-odd smoother {sap}: {info_eo[0]['iterations']} iterations, {t_eo * 1e3:.1f} ms")
         even_odd["mixed_speedup_over_plain"] = round(t_mixed / even_odd["mixed"]["time_s"], 3)
+
+    # the two-level method: the coarse correction of DD-alpha-AMG over the
+    # Schwarz smoother (FP32 post-smoothing for the FP32/FP16 workloads)
+    two_level = None
+    if args.amg_steps > 0:
+        apar = ddsap.default_amg_params()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(11)
+        v0 = torch.randn((apar.nvec, V, 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.amg_setup(w["m0"], v0, apar)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        del v0
+        torch.cuda.empty_cache()
+        sap_tl = "f64" if w["sap"] == "f64" else "f32"
+        one_solve(sap_tl, amg=True)
+        ctx.profile_enable(True)
+        ttl = []
+        for i in range(args.amg_steps):
+            t1 = time.perf_counter()
+            info_tl = one_solve(sap_tl, amg=True)
+            ttl.append(time.perf_counter() - t1)
+        prof_tl = ctx.profile_read()
+        ctx.profile_enable(False)
+        two_level = {
+            "setup_s": round(t_setup, 3), "time_s": round(float(np.median(ttl)), 4), "time_min_s": round(min(ttl), 4),
+            "repeats": len(ttl), "iterations": info_tl[0]["iterations"],
+            "rel_residual": max(i["rel_residual"] for i in info_tl), "smoother": sap_tl,
+            "speedup_over_sap_only": round(float(np.median(tsteps)) / float(np.median(ttl)), 3),
+            "params": {f: getattr(apar, f) for f, _ in apar._fields_},
+            "kernels_ms_per_solve": {k: round(v["total_ms"] / len(ttl), 3)
+                                     for k, v in sorted(prof_tl.items(), key=lambda kv: -kv[1]["total_ms"])[:8]}}
+        log(f"two-level: setup {t_setup:.2f} s, {info_tl[0]['iterations']} iterations, "
+            f"{float(np.median(ttl)) * 1e3:.1f} ms")
 
     # sensitivity of the mixed solve to the SAP cycles per preconditioner call
     # (the paper leaves the count open; 12 is the default)
@@ -544,8 +587,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic (seeded random SU(3) links, Gaussian right-hand sides)",
-        "config": {"workload": w["text"] + ("; the FP64 GPU path (FP64 smoother) timed alongside"
+        "config": {"workload": w["text"] + ("; the FP64 GPU path (FP64 smoother, same parameters) timed alongside"
                                             if args.fp64_steps > 0 else ""),
+                   "sap_cycles": params(w["sap"]).ncy,
                    "lattice": "x".join(map(str, dims)), "nrhs": nrhs,
                    "smoother": w["sap"], "parallelism": "single GPU", "link_compression": compressed,
                    **({"sap_half_fields": True} if args.sap_half_fields else {})},
@@ -572,6 +616,7 @@ def main():
         "iterations": {"mixed": infos[-1][0]["iterations"],
                        "fp64": None if info64 is None else info64[0]["iterations"]},
         "even_odd": even_odd,
+        "two_level": two_level,
         **({"ncy_sensitivity": ncy_scan} if ncy_scan else {}),
         "final_rel_residual": max(i["rel_residual"] for i in infos[-1]),
         "kernels": breakdown,

@@ -282,14 +282,14 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
  * [rhs][block][k] complex FP64 (device).  A context holds one setup; a new
  * dd_amg_setup replaces it. */
 typedef struct {
-    int nvec;        /* test vectors, 1..16 (8): 2 nvec coarse unknowns per block */
-    int setup_iters; /* inverse-iteration steps per test vector (3)               */
+    int nvec;        /* test vectors, 1..16 (12): 2 nvec coarse unknowns per block */
+    int setup_iters; /* inverse-iteration steps per test vector (6)               */
     int setup_ncy;   /* SAP cycles per setup step (4)                               */
     int setup_nmr;   /* MR steps per block in them (4)                              */
     int setup_prec;  /* precision of the setup's smoother, DD_F32 or DD_F64 (F32)   */
-    int adapt;       /* adaptive rounds with the two-grid method (1)                */
+    int adapt;       /* adaptive rounds with the two-grid method (2)                */
     int coarse_k;    /* GMRES steps of the coarse solve, 1..32 (16)                 */
-    int post_ncy;    /* SAP cycles after the coarse correction, >= 0 (4)            */
+    int post_ncy;    /* SAP cycles after the coarse correction, >= 0 (8)            */
     int post_nmr;    /* MR steps per block in them (4)                              */
 } dd_amg_params;
 
@@ -333,14 +333,16 @@ dd_status dd_amg_precondition(dd_ctx *ctx, const double *m0, const void *eta, vo
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of solves over resident gauge fields
  * ---------------------------------------------------------------------------
- * A server keeps several gauge fields resident (each with its own HIP stream
- * and a pool of right-hand-side slots sized from the HBM budget).  Requests
- * are queued first in, first out; a worker thread admits their right-hand
- * sides into free slots as earlier ones finish, fuses all slots of a field
- * into multi-RHS launches (the Arnoldi step is replayed as a captured
- * hipGraph) and overlaps different fields on their streams.  Each slot runs
- * its own FGMRES(m) to params tol, so a result does not depend on which other
- * requests share the launches beyond rounding. */
+ * A server keeps several gauge fields resident (each with its own HIP stream,
+ * its own worker thread and a pool of right-hand-side slots sized from the
+ * HBM budget).  Requests are queued first in, first out; a field's worker
+ * admits the right-hand sides of that field's requests into free slots as
+ * earlier ones finish and fuses all slots of the field into multi-RHS
+ * launches (the Arnoldi step is replayed as a captured hipGraph).  Fields
+ * advance independently -- a small lattice is not held to the step rate of a
+ * large one -- and overlap on the device through their streams.  Each slot
+ * runs its own FGMRES(m) to params tol, so a result does not depend on which
+ * other requests share the launches beyond rounding. */
 typedef struct dd_server dd_server;
 
 typedef struct {
@@ -365,7 +367,8 @@ typedef struct {
     double mean_ms;
     double wall_s;          /* first submit to last completion                     */
     double rhs_per_s;       /* rhs_done / wall_s                                   */
-    double busy_s;          /* worker time spent with work on the device           */
+    double busy_s;          /* worker time with work on the device, summed over the
+                               fields' workers (can exceed wall_s)                */
     size_t workspace_bytes; /* reserved slot workspace of all fields                */
 } dd_server_stats;
 

@@ -1,15 +1,16 @@
 // Continuous-batching solve server.
 //
-// Gauge fields stay resident on the device, each with its own HIP stream and
-// its own slot engine (engine.hip).  Requests (one field, one mass per
-// right-hand side, 1..n right-hand sides) enter a FIFO queue.  A worker
-// thread admits right-hand sides into free engine slots as soon as earlier
-// ones finish -- a request does not wait for a batch to drain -- and drives
-// every field's engine phase by phase: it enqueues the restart phase of all
-// fields, then finishes them, then enqueues the Arnoldi step of all fields,
-// then finishes those, so the fields' work overlaps on the device through
-// their streams while each field's slots share fused multi-RHS launches
-// (replayed hipGraphs).  Each field's slot pool is sized once from the HBM
+// Gauge fields stay resident on the device, each with its own HIP stream, its
+// own slot engine (engine.hip) and its own worker thread.  Requests (one
+// field, one mass per right-hand side, 1..n right-hand sides) enter a FIFO
+// queue.  A field's worker admits the right-hand sides of its field's
+// requests into free engine slots as soon as earlier ones finish -- a request
+// does not wait for a batch to drain -- and drives its engine phase by phase
+// (restart phase, then one Arnoldi step, each a fused multi-RHS launch
+// sequence replayed as a hipGraph).  Because every field advances on its own
+// thread and stream, a small lattice's requests proceed at its own step rate
+// instead of waiting on the largest field's steps, and the fields' work
+// overlaps on the device.  Each field's slot pool is sized once from the HBM
 // budget; a right-hand side is admitted only into a reserved slot, so the
 // workspace never exceeds the budget.  Completion times give per-request
 // latency; the statistics report p50/p99 beside throughput.
@@ -57,7 +58,7 @@ struct dd_server {
     std::deque<long> queue;
     std::unordered_map<long, Request> reqs;
     long next_id = 1;
-    std::thread worker;
+    std::vector<std::thread> workers; // one per field
     std::atomic<bool> stop{false};
     bool started = false;
     size_t used = 0;
@@ -88,13 +89,14 @@ double percentile(std::vector<double> v, double q)
     return v[lo] * (1 - f) + v[hi] * f;
 }
 
-// One pass of the worker: admit, run one engine iteration on every busy
-// field, harvest finished right-hand sides.  Returns false when idle.
-dd::Status work_once(dd_server *s, bool &did_work)
+// One pass of field fi's worker: admit its queued right-hand sides, run one
+// engine iteration if any slot is busy, harvest finished right-hand sides.
+dd::Status work_once(dd_server *s, int fi, bool &did_work)
 {
     did_work = false;
+    dd_server::Field &f = s->fields[fi];
     struct Adm {
-        int field, slot;
+        int slot;
         long req;
         int rhs;
         const double *b;
@@ -105,7 +107,10 @@ dd::Status work_once(dd_server *s, bool &did_work)
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto it = s->queue.begin(); it != s->queue.end();) {
             dd_server::Request &r = s->reqs[*it];
-            dd_server::Field &f = s->fields[r.field];
+            if (r.field != fi) {
+                ++it;
+                continue;
+            }
             while (r.next_rhs < r.nrhs) {
                 // a slot is taken when the engine has it free and no admission
                 // of this pass has reserved it yet
@@ -115,7 +120,7 @@ dd::Status work_once(dd_server *s, bool &did_work)
                 if (slot < 0) break;
                 f.slot_owner[slot] = {r.id, r.next_rhs};
                 const size_t vstride = (size_t)f.ctx->g.V * 24;
-                adm.push_back({r.field, slot, r.id, r.next_rhs, r.b + r.next_rhs * vstride, r.m0[r.next_rhs]});
+                adm.push_back({slot, r.id, r.next_rhs, r.b + r.next_rhs * vstride, r.m0[r.next_rhs]});
                 if (r.t_admit < 0) r.t_admit = now_s();
                 ++r.next_rhs;
             }
@@ -123,18 +128,14 @@ dd::Status work_once(dd_server *s, bool &did_work)
             else ++it;
         }
     }
-    for (auto &a : adm) DD_TRY(s->fields[a.field].eng->admit(a.slot, a.b, nullptr, a.m0, a.req, a.rhs));
-    bool busy = false;
-    for (auto &f : s->fields) busy |= f.eng->busy_slots() > 0;
-    if (!busy) return dd::Status::ok();
+    for (auto &a : adm) DD_TRY(f.eng->admit(a.slot, a.b, nullptr, a.m0, a.req, a.rhs));
+    if (f.eng->busy_slots() == 0) return dd::Status::ok();
     did_work = true;
     const double t0 = now_s();
-    for (auto &f : s->fields)
-        if (f.eng->busy_slots()) DD_TRY(f.eng->launch_restart());
-    for (auto &f : s->fields) DD_TRY(f.eng->finish_restart());
-    for (auto &f : s->fields)
-        if (f.eng->busy_slots()) DD_TRY(f.eng->launch_step());
-    for (auto &f : s->fields) DD_TRY(f.eng->finish_step());
+    DD_TRY(f.eng->launch_restart());
+    DD_TRY(f.eng->finish_restart());
+    if (f.eng->busy_slots()) DD_TRY(f.eng->launch_step());
+    DD_TRY(f.eng->finish_step());
     // harvest finished right-hand sides
     struct Fin {
         long req;
@@ -142,37 +143,33 @@ dd::Status work_once(dd_server *s, bool &did_work)
         dd_solve_info info;
     };
     std::vector<Fin> fin;
-    for (auto &f : s->fields) {
-        bool any = false;
-        for (int r = 0; r < f.eng->width(); ++r) {
-            dd::SlotState &st = f.eng->slot(r);
-            if (st.state != dd::SLOT_DONE) continue;
-            long req = f.slot_owner[r].first;
-            int rhs = f.slot_owner[r].second;
-            double *xdst = nullptr;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                auto it = s->reqs.find(req);
-                if (it != s->reqs.end()) xdst = it->second.x + (size_t)rhs * f.ctx->g.V * 24;
-            }
-            if (xdst) DD_TRY(f.eng->extract(r, xdst));
-            fin.push_back({req, rhs, st.info});
-            f.eng->release(r);
-            f.slot_owner[r] = {0, 0};
-            any = true;
+    for (int r = 0; r < f.eng->width(); ++r) {
+        dd::SlotState &st = f.eng->slot(r);
+        if (st.state != dd::SLOT_DONE) continue;
+        long req = f.slot_owner[r].first;
+        int rhs = f.slot_owner[r].second;
+        double *xdst = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            auto it = s->reqs.find(req);
+            if (it != s->reqs.end()) xdst = it->second.x + (size_t)rhs * f.ctx->g.V * 24;
         }
-        if (any) DD_HIP_TRY(hipStreamSynchronize(f.stream));
+        if (xdst) DD_TRY(f.eng->extract(r, xdst));
+        fin.push_back({req, rhs, st.info});
+        f.eng->release(r);
+        f.slot_owner[r] = {0, 0};
     }
+    if (!fin.empty()) DD_HIP_TRY(hipStreamSynchronize(f.stream));
     const double t1 = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     s->busy_s += t1 - t0;
-    for (auto &fi : fin) {
-        auto it = s->reqs.find(fi.req);
+    for (auto &fi2 : fin) {
+        auto it = s->reqs.find(fi2.req);
         if (it == s->reqs.end()) continue;
         dd_server::Request &r = it->second;
-        r.info[fi.rhs] = fi.info;
-        if (fi.info.status != DD_OK && r.status == DD_OK) r.status = fi.info.status;
-        s->iterations += fi.info.iterations;
+        r.info[fi2.rhs] = fi2.info;
+        if (fi2.info.status != DD_OK && r.status == DD_OK) r.status = fi2.info.status;
+        s->iterations += fi2.info.iterations;
         ++s->rhs_done;
         if (++r.done_rhs == r.nrhs) {
             r.complete = true;
@@ -185,18 +182,18 @@ dd::Status work_once(dd_server *s, bool &did_work)
     return dd::Status::ok();
 }
 
-void worker_main(dd_server *s)
+void worker_main(dd_server *s, int fi)
 {
     if (hipSetDevice(s->device) != hipSuccess) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->fatal = DD_HIP_ERROR;
-        s->err = "server: hipSetDevice failed in the worker";
+        s->err = "server: hipSetDevice failed in a worker";
         s->cv_done.notify_all();
         return;
     }
     while (!s->stop.load()) {
         bool did = false;
-        dd::Status st = work_once(s, did);
+        dd::Status st = work_once(s, fi, did);
         if (!st.good()) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->fatal = st.code;
@@ -207,7 +204,9 @@ void worker_main(dd_server *s)
                     kv.second.status = st.code;
                 }
             s->queue.clear();
+            s->stop.store(true);
             s->cv_done.notify_all();
+            s->cv_work.notify_all();
             return;
         }
         if (!did) {
@@ -355,9 +354,10 @@ dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m
     if (!s->started) {
         s->started = true;
         try {
-            s->worker = std::thread(worker_main, s);
+            for (int fi = 0; fi < (int)s->fields.size(); ++fi) s->workers.emplace_back(worker_main, s, fi);
         } catch (...) {
-            s->err = "server: could not start the worker thread";
+            s->err = "server: could not start the worker threads";
+            s->stop.store(true);
             return DD_HIP_ERROR;
         }
     }
@@ -374,7 +374,7 @@ dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m
     *request_id = r.id;
     s->queue.push_back(r.id);
     s->reqs.emplace(r.id, std::move(r));
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     return DD_OK;
 }
 
@@ -442,7 +442,8 @@ dd_status dd_server_destroy(dd_server *s)
     if (!s) return DD_INVALID_ARG;
     s->stop.store(true);
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (auto &w : s->workers)
+        if (w.joinable()) w.join();
     (void)hipSetDevice(s->device);
     for (auto &f : s->fields) {
         f.eng.reset();

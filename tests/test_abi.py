@@ -49,3 +49,7 @@ def test_abi_version_and_defaults(lib):
     assert (p.m, p.tol, p.max_restarts, p.ncy, p.nmr, p.sap_prec, p.sap_eo) == (20, 1e-10, 100, 12, 4, ddsap.DD_F32, 0)
     c = ddsap.default_server_config()
     assert (c.sap_prec, c.use_graphs, c.sap_eo, c.ncy, c.nmr, c.sap_half_fields) == (ddsap.DD_F32, 1, 0, 12, 4, 0)
+    a = ddsap.default_amg_params()
+    assert (a.nvec, a.setup_iters, a.setup_ncy, a.setup_nmr, a.setup_prec, a.adapt, a.coarse_k, a.post_ncy,
+            a.post_nmr) == (12, 6, 4, 4, ddsap.DD_F32, 2, 16, 8, 4)
+    assert p.amg == 0
