@@ -85,9 +85,17 @@ def parse():
                     help="also time the oracle operator on the workload lattice, one SAP cycle there and the full "
                          "32^3x64 solve (minutes of host time)")
     ap.add_argument("--serve", action="store_true", help="run the continuous-batching serving workload instead")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-budget-gb", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving phase")
+    ap.add_argument("--serve-budget-gb", type=int, default=200, help="HBM budget of the slot workspaces")
+    ap.add_argument("--serve-inflight", type=int, default=16,
+                    help="requests outstanding in the saturated phase (36 slots hold about six requests)")
+    ap.add_argument("--serve-hold-gb", type=int, default=48,
+                    help="device memory for the right-hand sides and solutions of requests in flight")
+    ap.add_argument("--serve-fp64-requests", type=int, default=48, help="requests of the FP64-path comparison")
     ap.add_argument("--no-standalone", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="multi-RHS workloads: skip the one-at-a-time solves (e.g. for counter runs that should "
+                         "see only fused launches)")
     ap.add_argument("--sap-half-fields", action="store_true",
                     help="the FP32 smoother reads FP16 links and clover (dd_set_sap_half_fields)")
     ap.add_argument("--ncy-scan", default="",
@@ -231,91 +239,137 @@ SERVE_FIELDS = [((16, 16, 16, 16), 0.5, 1), ((24, 24, 24, 48), 0.5, 2), ((32, 32
 
 
 def serve_main(args):
-    """Serving workload: three resident fields, requests with m0 ~ U[-0.38,-0.2] and 1..12 Gaussian RHS,
-    first a burst (saturation throughput), then Poisson arrivals at 0.7x that load; the same burst is
-    then served with the FP64 smoother (the plain FP64 GPU path) for comparison."""
+    """Serving workload: three resident fields (16^4, 24^3x48, 32^3x64), requests on a uniformly chosen
+    field with m0 ~ U[-0.38,-0.2] per right-hand side and 1..12 Gaussian right-hand sides, solved to 1e-10.
+    First a closed loop that keeps the server saturated (at most --serve-inflight requests outstanding)
+    gives the saturation throughput; then Poisson arrivals at 0.5x and 0.9x that request rate give
+    p50/p99 latency (overall and per lattice); the plain FP64 GPU path (FP64 smoother) serves a shorter
+    saturated run for comparison.  Right-hand sides are generated on the device when a request is
+    submitted and freed when it is delivered, so device memory stays bounded."""
     import torch
     from paper_1710_07041_amd import ddsap, synth
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     fields = [(dims, synth.random_su3_links(dims, eps, seed=seed)) for dims, eps, seed in SERVE_FIELDS]
     vols = [synth.volume(dims) for dims, _ in fields]
+    names = ["x".join(map(str, dims)) for dims, _ in fields]
     log(f"serving fields generated in {time.perf_counter() - t0:.1f} s")
     gen = torch.Generator(device="cuda")
 
     def make_server(prec):
-        srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb << 30, max_width=12, use_graphs=1, sap_prec=prec,
-                           sap_half_fields=1 if args.sap_half_fields and prec == "f32" else 0)
+        srv = ddsap.Server(hbm_budget_bytes=args.serve_budget_gb * 10 ** 9, max_width=12, use_graphs=1,
+                           sap_prec=prec, sap_half_fields=1 if args.sap_half_fields and prec == "f32" else 0)
         fids = [srv.add_field(dims, U, 1.0) for dims, U in fields]
         return srv, fids, [srv.field_info(f)[0] for f in fids]
 
-    def make_reqs(rng, first, n):
-        out = []
-        for k in range(first, first + n):
+    def plan(seed, n):
+        rng = np.random.default_rng(seed)
+        reqs = []
+        for k in range(n):
             fi = int(rng.integers(0, len(fields)))
             nrhs = int(rng.integers(1, 13))
-            m0 = rng.uniform(-0.38, -0.2, size=nrhs)
-            gen.manual_seed(1000 + k)
-            b = torch.randn((nrhs, vols[fi], 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
-            out.append((fi, m0, b))
-        return out
+            reqs.append((fi, rng.uniform(-0.38, -0.2, size=nrhs), 1000 * seed + k))
+        return reqs
 
-    def run(srv, fids, reqs, arrivals):
-        outs = []
+    def run(srv, fids, reqs, arrivals=None, inflight=None):
+        """Submit reqs at their arrival times (seconds from the start) or, without arrivals, whenever
+        fewer than `inflight` are outstanding; deliver completed ones as they finish."""
+        out = {}  # rid -> (fi, nrhs, b, x)
+        lat, lat_f, res = [], [[] for _ in fields], 0.0
+        nrhs_tot = 0
+
+        def deliver(block):
+            nonlocal res
+            for rid in list(out):
+                fi, n, b, x = out[rid]
+                if block:
+                    st, info, l = srv.wait(rid)
+                    done = True
+                else:
+                    done, st, info, l = srv.poll(rid)
+                if not done:
+                    continue
+                if st != ddsap.DD_OK:
+                    raise RuntimeError(f"served solve failed: {ddsap.STATUS_NAMES[st]}")
+                lat.append(l)
+                lat_f[fi].append(l)
+                res = max(res, max(i["rel_residual"] for i in info))
+                del out[rid]
+                if block:
+                    return
+
+        held = lambda: sum(2 * o[1] * vols[o[0]] * 192 for o in out.values())  # bytes of b and x
+        capped = 0
         t_start = time.perf_counter()
-        for (fi, m0, b), ta in zip(reqs, arrivals):
-            dt = t_start + ta - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
+        for k, (fi, m0, seed) in enumerate(reqs):
+            if arrivals is not None:
+                while True:
+                    deliver(False)
+                    dt = t_start + arrivals[k] - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.002))
+            else:
+                deliver(False)
+                while len(out) >= inflight:
+                    deliver(True)
+            if out and held() > args.serve_hold_gb * 10 ** 9:
+                capped += 1  # device memory for requests in flight: wait for one to finish
+                while out and held() > args.serve_hold_gb * 10 ** 9:
+                    deliver(True)
+            gen.manual_seed(seed)
+            n = len(m0)
+            b = torch.randn((n, vols[fi], 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
             x = torch.zeros_like(b)
-            outs.append((srv.submit(fids[fi], m0, b, x), fi, b.shape[0]))
-        lat, res, nrhs_tot = [], 0.0, 0
-        for rid, fi, n in outs:
-            st, info, l = srv.wait(rid)
-            if st != ddsap.DD_OK:
-                raise RuntimeError(f"served solve failed: {ddsap.STATUS_NAMES[st]}")
-            lat.append(l)
-            res = max(res, max(i["rel_residual"] for i in info))
+            out[srv.submit(fids[fi], m0, b, x)] = (fi, n, b, x)
             nrhs_tot += n
+        while out:
+            deliver(True)
         wall = time.perf_counter() - t_start
-        return {"requests": len(reqs), "rhs": nrhs_tot, "wall_s": round(wall, 3), "rhs_per_s": round(nrhs_tot / wall, 2),
-                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                "mean_ms": round(float(np.mean(lat)), 2), "max_rel_residual": res}
+        pct = lambda v, q: round(float(np.percentile(v, q)), 2) if v else None
+        return {"requests": len(reqs), "rhs": nrhs_tot, "wall_s": round(wall, 3),
+                "requests_per_s": round(len(reqs) / wall, 3), "rhs_per_s": round(nrhs_tot / wall, 2),
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": round(float(np.mean(lat)), 2),
+                "per_lattice": {names[f]: {"requests": len(lat_f[f]), "p50_ms": pct(lat_f[f], 50),
+                                           "p99_ms": pct(lat_f[f], 99)} for f in range(len(fields))},
+                "max_rel_residual": res, "submits_held_for_memory": capped}
 
     n = args.serve_requests
-    # mixed precision: FP32 smoother
     srv, fids, widths = make_server("f32")
     log(f"mixed server: slots per field {widths}")
-    rng = np.random.default_rng(7)
-    sat = run(srv, fids, make_reqs(rng, 0, n), [0.0] * n)
+    sat = run(srv, fids, plan(7, n), inflight=args.serve_inflight)
     torch.cuda.empty_cache()
-    log(f"burst: {sat}")
-    rate_req = 0.7 * sat["rhs_per_s"] / 6.5  # requests per second at 0.7x the saturation load
-    reqs = make_reqs(rng, n, n)
-    arr = np.cumsum(rng.exponential(1.0 / rate_req, size=n))
-    arr[0] = 0.0
-    pois = run(srv, fids, reqs, list(arr))
-    del reqs
-    log(f"poisson 0.7x: {pois}")
+    log(f"saturation: {sat}")
+    poisson = {}
+    for k, load in enumerate((0.5, 0.9)):
+        rate = load * sat["requests_per_s"]
+        rng = np.random.default_rng(100 + k)
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        arr -= arr[0]
+        poisson[f"{load}x"] = run(srv, fids, plan(8 + k, n), arrivals=list(arr))
+        torch.cuda.empty_cache()
+        log(f"poisson {load}x: {poisson[f'{load}x']}")
     st = srv.stats()
     srv.close()
     torch.cuda.empty_cache()
-    # the same burst with the FP64 smoother
+    # the plain FP64 GPU path on a shorter saturated run
     srv64, fids64, widths64 = make_server("f64")
     log(f"FP64 server: slots per field {widths64}")
-    sat64 = run(srv64, fids64, make_reqs(np.random.default_rng(7), 0, n), [0.0] * n)
+    n64 = max(1, args.serve_fp64_requests)
+    sat64 = run(srv64, fids64, plan(7, n64), inflight=args.serve_inflight)
     srv64.close()
-    log(f"FP64 burst: {sat64}")
+    log(f"FP64 saturation: {sat64}")
     out = {
         "metric": "serving: RHS/s at saturation, p50/p99 latency under Poisson load (continuous batching)",
-        "value": sat["rhs_per_s"], "unit": "RHS/s", "n_gpus": 1, "steps": 2 * n, "warmup": 0,
+        "value": sat["rhs_per_s"], "unit": "RHS/s", "n_gpus": 1, "steps": n, "warmup": 0,
         "ms_per_step": round(1e3 * sat["wall_s"] / max(sat["requests"], 1), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "serving: resident 16^4, 24^3x48, 32^3x64 (eps=0.5, csw=1), m0~U[-0.38,-0.2], "
                                "1-12 Gaussian RHS per request, SAP FP32 + FGMRES(20) FP64 to 1e-10, "
-                               f"HBM budget {args.serve_budget_gb} GiB", "slots_per_field": widths,
+                               f"{n} requests per phase, HBM budget {args.serve_budget_gb} GB",
+                   "slots_per_field": widths, "saturation_inflight": args.serve_inflight,
                    **({"sap_half_fields": True} if args.sap_half_fields else {})},
-        "serving": {"saturation": sat, "poisson_0.7x": pois, "server_stats": st,
+        "serving": {"saturation": sat, "poisson": poisson, "server_stats": st,
                     "fp64_smoother": {"slots_per_field": widths64, "saturation": sat64,
                                       "mixed_over_fp64_rhs_per_s": round(sat["rhs_per_s"] / sat64["rhs_per_s"], 3)}},
     }
@@ -372,23 +426,29 @@ def main():
             raise RuntimeError(f"solve failed: {ddsap.STATUS_NAMES[st]} {info}")
         return info
 
-    # a plain 1 GiB device copy: the reference a counter run scales FETCH/WRITE
-    # by, and the achievable-bandwidth line (2 GiB moved per copy; median of 10)
+    # a plain 1 GiB device copy (torch's): the reference a counter run scales
+    # FETCH/WRITE by; and the achievable-bandwidth line, the library's own
+    # streaming copy of 4 GiB (8 GiB moved per copy; median of 10)
     ca = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
     cb = torch.empty_like(ca)
     cb.copy_(ca)
+    del ca, cb
+    sa = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    sb = torch.empty_like(sa)
+    ddsap.stream_copy(sa, sb, sa.numel() * 4)
     torch.cuda.synchronize()
     ct = []
     for _ in range(10):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        cb.copy_(ca)
+        ddsap.stream_copy(sa, sb, sa.numel() * 4)
         e1.record()
         e1.synchronize()
         ct.append(e0.elapsed_time(e1) * 1e-3)
-    copy_gbs = 2.0 * ca.numel() * 4 / float(np.median(ct)) / 1e9
-    del ca, cb
-    log(f"device copy: {copy_gbs:.0f} GB/s")
+    copy_gbs = 2.0 * sa.numel() * 4 / float(np.median(ct)) / 1e9
+    del sa, sb
+    torch.cuda.empty_cache()
+    log(f"streaming copy: {copy_gbs:.0f} GB/s")
 
     for i in range(args.warmup):
         info = one_solve(w["sap"])
@@ -501,7 +561,7 @@ def main():
 
     # multi-RHS: the same right-hand sides solved one at a time, for the fusion gain
     sequential = None
-    if nrhs > 1:
+    if nrhs > 1 and not args.no_sequential:
         bs = [bd[r:r + 1].clone() for r in range(nrhs)]
         xs = torch.zeros_like(bs[0])
         torch.cuda.synchronize()

@@ -447,6 +447,13 @@ typedef struct {
     double flops;
 } dd_kernel_stat;
 
+/* Copy bytes (a multiple of 16) from src to dst (device pointers, not
+ * overlapping) on stream with a plain streaming kernel: 16-byte
+ * non-temporal loads and stores, grid-stride.  The achievable HBM bandwidth
+ * it reaches (2 * bytes / time) is the reference line the operator and
+ * smoother rates are compared with.  DD_INVALID_ARG for bad sizes. */
+dd_status dd_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Switch event timing on (1) or off (0); switching on clears the counters. */
 dd_status dd_profile_enable(dd_ctx *ctx, int enable);
 

@@ -479,6 +479,17 @@ dd_status dd_debug_poison_half_smoother(dd_ctx *ctx, int count)
     return DD_OK;
 }
 
+dd_status dd_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (!src || !dst || bytes == 0 || bytes % 16 != 0) return DD_INVALID_ARG;
+    try {
+        dd::Status s = dd::stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+        return s.code;
+    } catch (...) {
+        return DD_HIP_ERROR;
+    }
+}
+
 dd_status dd_profile_enable(dd_ctx *ctx, int enable)
 {
     if (!ctx) return DD_INVALID_ARG;

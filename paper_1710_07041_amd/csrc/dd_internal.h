@@ -220,6 +220,9 @@ Status amg_reserve(dd_ctx *ctx, AmgWork &wk, int W, int prec, int kmax);
 Status run_two_grid(dd_ctx *ctx, AmgWork &wk, int W, const void *eta, const long *eta_off, int prec, void *z,
                     const long *z_off, const double *m0_dev, const int *active);
 
+// profile.hip: streaming device copy (bytes a multiple of 16)
+Status stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+
 // engine.hip
 Status solve(dd_ctx *ctx, const double *m0, const double *b, double *x, int nrhs, const dd_params &p,
              dd_solve_info *info);

@@ -41,7 +41,7 @@ EXPORTS = [
     "dd_apply_D_block", "dd_sap", "dd_sap_eo", "dd_sap_noalloc", "dd_solve", "dd_amg_default_params",
     "dd_amg_setup", "dd_amg_coarse_size", "dd_amg_interpolation", "dd_amg_coarse_operator", "dd_amg_restrict",
     "dd_amg_prolong", "dd_amg_coarse_apply", "dd_amg_coarse_solve", "dd_amg_precondition", "dd_debug_poison_half_smoother", "dd_profile_enable",
-    "dd_profile_read",
+    "dd_profile_read", "dd_stream_copy",
     "dd_server_default_config", "dd_server_create", "dd_server_add_field", "dd_server_field_info",
     "dd_server_submit", "dd_server_poll", "dd_server_wait", "dd_server_get_stats", "dd_server_last_error",
     "dd_server_destroy",
@@ -121,6 +121,7 @@ _sigs = {
     "dd_amg_coarse_solve": ([_vp, _dp, _vp, _vp, _i, _i], _i),
     "dd_amg_precondition": ([_vp, _dp, _vp, _vp, _i, _i], _i),
     "dd_profile_enable": ([_vp, _i], _i),
+    "dd_stream_copy": ([_vp, _vp, _sz, _vp], _i),
     "dd_server_default_config": ([ctypes.POINTER(dd_server_config)], None),
     "dd_server_create": ([ctypes.POINTER(dd_server_config), ctypes.POINTER(_vp)], _i),
     "dd_server_add_field": ([_vp, _ip, _ip, _vp, _d, _i, _ip], _i),
@@ -351,6 +352,15 @@ class Context:
             raise DDError(DD_HIP_ERROR, _lib.dd_last_error(self._h).decode())
         return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
                                        "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(n)}
+
+
+def stream_copy(src, dst, nbytes, stream=None):
+    """dd_stream_copy on torch's current stream (or the given one)."""
+    import torch
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    s = _lib.dd_stream_copy(_vp(_ptr(src)), _vp(_ptr(dst)), int(nbytes), _vp(st))
+    if s != DD_OK:
+        raise DDError(s, "dd_stream_copy failed")
 
 
 def default_amg_params() -> dd_amg_params:
