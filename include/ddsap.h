@@ -270,7 +270,7 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
  *                 every mass; the test vectors are tuned to the setup mass);
  *   coarse solve  coarse_k steps of GMRES from zero (the least-residual
  *                 vector of the Krylov space), on the device, FP64 vectors
- *                 and an FP32 copy of D_c;
+ *                 and an FP16 copy of D_c;
  *   two-grid B    psi_0 = P x_c with x_c the coarse solve of
  *                 D_c x_c = P^+ eta, then psi = psi_0 + SAP(eta - D psi_0)
  *                 with post_ncy cycles of post_nmr MR steps.
@@ -318,7 +318,8 @@ dd_status dd_amg_coarse_operator(dd_ctx *ctx, double *Dc_host);
 dd_status dd_amg_restrict(dd_ctx *ctx, const void *x, double *xc, int prec, int nrhs);
 dd_status dd_amg_prolong(dd_ctx *ctx, const double *xc, void *x, int prec, int nrhs);
 
-/* yc = (D_c + m0[r]) xc for each right-hand side r (m0: host, nrhs values). */
+/* yc = (D_c + m0[r]) xc for each right-hand side r (m0: host, nrhs values),
+ * with the FP16 copy of D_c that the coarse solve uses. */
 dd_status dd_amg_coarse_apply(dd_ctx *ctx, const double *m0, const double *xc, double *yc, int nrhs);
 
 /* xc = k steps of GMRES from zero on (D_c + m0[r]) xc = bc (1 <= k <= 32;

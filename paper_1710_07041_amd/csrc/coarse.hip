@@ -26,7 +26,9 @@
 //          component = (spin - 2c) * 3 + colour; FP64 master, FP32 copy;
 //   D_c    [block][d][column k'][row k], d = 0 the block itself, 1 + 2 mu
 //          the +mu neighbour, 2 + 2 mu the -mu neighbour; row/column index
-//          k = c * N + i; FP64 master, FP32 copy read by the solve;
+//          k = c * N + i; FP64 master, FP16 copy read by the coarse solve
+//          (the coarse system is solved only approximately, and its nine
+//          blocks per row are the largest array the solve streams);
 //   coarse vectors [slot][block][k], FP64.
 // Everything a block or a coarse site reduces is summed in a fixed order
 // (DPP within a wavefront, then the wavefronts in order), so results are
@@ -171,7 +173,7 @@ __device__ __forceinline__ void load_col(const double2 *__restrict__ Pd, int b, 
 
 __global__ __launch_bounds__(BS) void k_amg_build(const double2 *__restrict__ Pd, const double2 *__restrict__ links,
                                                   const double2 *__restrict__ clov, double2 *__restrict__ Ad,
-                                                  float2 *__restrict__ Af, AGeom a)
+                                                  __half2 *__restrict__ Ah, AGeom a)
 {
     __shared__ Red R;
     const int b = blockIdx.x, d = blockIdx.y, s = threadIdx.x, lane = s & 63, wave = s >> 6;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(BS) void k_amg_build(const double2 *__restrict__ Pd
             // all hops of this direction stay in the block: counted in d = 0
             for (int e = s; e < N2 * N2; e += BS) {
                 Ad[((long)b * 9 + d) * N2 * N2 + e] = make_double2(0, 0);
-                Af[((long)b * 9 + d) * N2 * N2 + e] = make_float2(0, 0);
+                Ah[((long)b * 9 + d) * N2 * N2 + e] = __floats2half2_rn(0.f, 0.f);
             }
             return;
         }
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(BS) void k_amg_build(const double2 *__restrict__ Pd
             const cx<double> v = wave_get(R, s);
             const long o = (((long)b * 9 + d) * N2 + kp) * N2 + s;
             stc(Ad + o, v);
-            stc(Af + o, v);
+            stc(Ah + o, v);
         }
         __syncthreads();
     }
@@ -340,7 +342,8 @@ __device__ __forceinline__ int cnbr(const Geom &g, int b, const int bc[4], int d
 }
 
 // One thread per (coarse site, row): y_r = (D_c + m0_r) x_r for the slots
-// (slot r reads x + r * xs and writes y + r * ys; [nblocks][2N] each).
+// (slot r reads x + r * xs and writes y + r * ys; [nblocks][2N] each), the
+// FP16 copy of D_c with FP64 vectors and accumulation.
 // The nine 2N x 2N blocks of a row are read column by column, so the 2N
 // threads of a coarse site read consecutive entries; x of the source block
 // is the same for all of them.
@@ -580,7 +583,7 @@ __global__ __launch_bounds__(CTPB) void k_cg_next(double2 *__restrict__ V, const
 // N2 = 2N is a compile-time constant so that the loads of a block row are
 // issued together (a run-time loop waits on each pair of loads in turn)
 template <int N2>
-__global__ __launch_bounds__(CTPB) void k_coarse_apply(const float2 *__restrict__ Af, const double2 *__restrict__ x,
+__global__ __launch_bounds__(CTPB) void k_coarse_apply(const __half2 *__restrict__ Ah, const double2 *__restrict__ x,
                                                        long xs, double2 *__restrict__ y, long ys,
                                                        const GState *__restrict__ st, CArgs a)
 {
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(CTPB) void k_coarse_apply(const float2 *__restrict_
 #pragma unroll 1
         for (int d = 0; d < 9; ++d) {
             const int src = d == 0 ? b : cnbr(a.g, b, bc, d);
-            const float2 *Ac = Af + ((long)b * 9 + d) * N2 * N2 + k;
+            const __half2 *Ac = Ah + ((long)b * 9 + d) * N2 * N2 + k;
             const double2 *xsrc = xr + (long)src * N2;
 #pragma unroll 16
             for (int kp = 0; kp < N2; ++kp) cmac(acc, ldc<double>(Ac + (long)kp * N2), ldc<double>(xsrc + kp));
@@ -606,11 +609,11 @@ __global__ __launch_bounds__(CTPB) void k_coarse_apply(const float2 *__restrict_
     }
 }
 
-void coarse_apply(int N, dim3 grid, hipStream_t st, const float2 *Af, const double2 *x, long xs, double2 *y, long ys,
+void coarse_apply(int N, dim3 grid, hipStream_t st, const __half2 *Ah, const double2 *x, long xs, double2 *y, long ys,
                   const GState *S, const CArgs &a)
 {
     switch (N) {
-#define DD_CA(n) case n: k_coarse_apply<2 * n><<<grid, CTPB, 0, st>>>(Af, x, xs, y, ys, S, a); break;
+#define DD_CA(n) case n: k_coarse_apply<2 * n><<<grid, CTPB, 0, st>>>(Ah, x, xs, y, ys, S, a); break;
         DD_CA(1) DD_CA(2) DD_CA(3) DD_CA(4) DD_CA(5) DD_CA(6) DD_CA(7) DD_CA(8)
         DD_CA(9) DD_CA(10) DD_CA(11) DD_CA(12) DD_CA(13) DD_CA(14) DD_CA(15) DD_CA(16)
 #undef DD_CA
@@ -738,7 +741,7 @@ struct AmgWork {
 struct AmgData {
     int N = 0;
     dd_amg_params p{};
-    DevBuf Pd, Pf, Ad, Af;
+    DevBuf Pd, Pf, Ad, Ah; // P FP64 / FP32; D_c FP64 / FP16 (the copy the coarse solve reads)
     AmgWork work; // standalone calls and the setup's adaptive rounds
 };
 
@@ -823,7 +826,7 @@ Status coarse_gmres(dd_ctx *ctx, AmgWork &wk, int W, int k, const double *m0_dev
     k_cg_init<<<grid, CTPB, 0, st>>>(wk.xb.as<double2>(), V, wk.partN.as<double2>(), S, a, kmax);
     for (int j = 0; j < k; ++j) {
         // w = (D_c + m0) v_j
-        coarse_apply(A.N, agrid, st, A.Af.as<float2>(), V + (long)j * nrow, (long)(kmax + 1) * nrow, w, nrow, S, a);
+        coarse_apply(A.N, agrid, st, A.Ah.as<__half2>(), V + (long)j * nrow, (long)(kmax + 1) * nrow, w, nrow, S, a);
         k_cg_dots<<<grid, CTPB, 0, st>>>(V, w, wk.partA.as<double2>(), S, a, kmax, j);
         k_cg_orth<<<grid, CTPB, 0, st>>>(V, w, wk.partA.as<double2>(), wk.partB.as<double2>(), S, a, kmax, j, 1);
         k_cg_orth<<<grid, CTPB, 0, st>>>(V, w, wk.partB.as<double2>(), wk.partN.as<double2>(), S, a, kmax, j, 2);
@@ -915,7 +918,7 @@ Status build_P_Dc(dd_ctx *ctx, const double2 *tv64)
     ag.r12 = ctx->link_r12 ? 1 : 0;
     k_amg_build<<<dim3(nb, 9), BS, 0, ctx->stream>>>(A.Pd.as<double2>(), ctx->links[DD_F64].as<double2>(),
                                                      ctx->clover[DD_F64].as<double2>(), A.Ad.as<double2>(),
-                                                     A.Af.as<float2>(), ag);
+                                                     A.Ah.as<__half2>(), ag);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }
@@ -953,7 +956,7 @@ Status amg_setup(dd_ctx *ctx, double m0, const double *v0, const dd_amg_params &
     DD_TRY(A.Pf.alloc(pbytes * 8));
     const size_t abytes = (size_t)ctx->g.nblocks * 9 * 4 * N * N;
     DD_TRY(A.Ad.alloc(abytes * 16));
-    DD_TRY(A.Af.alloc(abytes * 8));
+    DD_TRY(A.Ah.alloc(abytes * 4));
     DevBuf ta, tb, t64, part;
     DD_TRY(ta.alloc(spinor_bytes(ctx->g, sp, N)));
     DD_TRY(tb.alloc(spinor_bytes(ctx->g, sp, N)));
@@ -1030,7 +1033,7 @@ Status amg_standalone(dd_ctx *ctx, int op, const double *m0, int nrhs, const voi
         break;
     case 2: // coarse apply
         coarse_apply(N, dim3((unsigned)std::min<long>(((long)ncoarse(ctx) + CTPB - 1) / CTPB, 8192), nrhs),
-                     ctx->stream, A.Af.as<float2>(), static_cast<const double2 *>(in), (long)ncoarse(ctx),
+                     ctx->stream, A.Ah.as<__half2>(), static_cast<const double2 *>(in), (long)ncoarse(ctx),
                      static_cast<double2 *>(out), (long)ncoarse(ctx), nullptr, a);
         break;
     case 3: // coarse solve with k steps

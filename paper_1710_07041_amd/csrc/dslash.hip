@@ -96,6 +96,43 @@ __device__ __forceinline__ void hop_switch(int k, const vec2_t<SI> *__restrict__
     }
 }
 
+// The staged form (one right-hand side per workgroup): the block's own input
+// spinor is in LDS, so an in-block neighbour is read from there and only a
+// neighbour across the block face comes from memory (those lanes alone).
+template <int K, typename SI, typename A>
+__device__ __forceinline__ void hop_stg(const vec2_t<SI> *__restrict__ g, const vec2_t<SI> *stg, int sn, bool inb,
+                                        const cx<A> U[9], A kk, cx<A> acc[12])
+{
+    vec2_t<SI> raw[12];
+    if (inb) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) raw[c] = stg[c * BS + sn];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) raw[c] = g[c * BS];
+    }
+    cx<A> psi[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&raw[c]);
+    hop_k<K, A>(psi, U, kk, acc);
+}
+
+template <typename SI, typename A>
+__device__ __forceinline__ void hop_stg_switch(int k, const vec2_t<SI> *__restrict__ g, const vec2_t<SI> *stg, int sn,
+                                               bool inb, const cx<A> U[9], A kk, cx<A> acc[12])
+{
+    switch (k) {
+    case 0: hop_stg<0, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 1: hop_stg<1, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 2: hop_stg<2, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 3: hop_stg<3, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 4: hop_stg<4, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 5: hop_stg<5, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    case 6: hop_stg<6, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    default: hop_stg<7, SI, A>(g, stg, sn, inb, U, kk, acc); break;
+    }
+}
+
 template <typename SF, typename A>
 __device__ __forceinline__ void load_hop_link(const vec2_t<SF> *__restrict__ links, int b, int s, int k, int bn,
                                               int sn, bool r12, cx<A> U[9])
@@ -105,12 +142,91 @@ __device__ __forceinline__ void load_hop_link(const vec2_t<SF> *__restrict__ lin
     load_link<A>(links + ((long)lb * 4 + mu) * 9 * BS + ls, r12, U);
 }
 
-template <bool BLOCKONLY, bool PF, bool PAIR, int RT, typename SI, typename SF, typename A>
+template <bool BLOCKONLY, bool PF, bool PAIR, int RT, typename SI, typename SF, typename A, bool STG = false>
 __device__ __forceinline__ void hops(const vec2_t<SI> *__restrict__ in, const vec2_t<SF> *__restrict__ links,
                                      const DArgs &a, int b, const int bc[4], int r0, const long ro[RT], int s,
-                                     cx<A> acc[RT][12])
+                                     cx<A> acc[RT][12], const vec2_t<SI> *stg = nullptr)
 {
-    if constexpr (PAIR && !BLOCKONLY && RT == 1 && sizeof(SI) <= 4) {
+    if constexpr (STG && PAIR) {
+        // FP32 input: the pair form below with the in-block neighbours from
+        // the LDS copy of the block
+        static_assert(!BLOCKONLY && RT == 1, "the staged forms take one right-hand side");
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            int bf, sf, gf, bb, sb, gb;
+            bool inf, inbk;
+            neighbour_rt(a.g, b, bc, s, mu, +1, bf, sf, gf, inf);
+            neighbour_rt(a.g, b, bc, s, mu, -1, bb, sb, gb, inbk);
+            vec2_t<SI> pf[12], pb[12];
+            cx<A> Uf[9], Ub[9];
+            if (inf) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) pf[c] = stg[c * BS + sf];
+            } else {
+                const vec2_t<SI> *qf = in + ro[0] + ((long)bf * a.nrhs + r0) * 12 * BS + sf;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) pf[c] = qf[c * BS];
+            }
+            load_hop_link<SF, A>(links, b, s, 2 * mu, bf, sf, a.r12, Uf);
+            if (inbk) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) pb[c] = stg[c * BS + sb];
+            } else {
+                const vec2_t<SI> *qb = in + ro[0] + ((long)bb * a.nrhs + r0) * 12 * BS + sb;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) pb[c] = qb[c * BS];
+            }
+            load_hop_link<SF, A>(links, b, s, 2 * mu + 1, bb, sb, a.r12, Ub);
+            cx<A> psi[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&pf[c]);
+            const A kf = (A)(-0.5 * gf), kb = (A)(-0.5 * gb);
+            switch (mu) {
+            case 0: hop_k<0, A>(psi, Uf, kf, acc[0]); break;
+            case 1: hop_k<2, A>(psi, Uf, kf, acc[0]); break;
+            case 2: hop_k<4, A>(psi, Uf, kf, acc[0]); break;
+            default: hop_k<6, A>(psi, Uf, kf, acc[0]); break;
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = ldc<A>(&pb[c]);
+            switch (mu) {
+            case 0: hop_k<1, A>(psi, Ub, kb, acc[0]); break;
+            case 1: hop_k<3, A>(psi, Ub, kb, acc[0]); break;
+            case 2: hop_k<5, A>(psi, Ub, kb, acc[0]); break;
+            default: hop_k<7, A>(psi, Ub, kb, acc[0]); break;
+            }
+        }
+    } else if constexpr (STG) {
+        static_assert(PF && !BLOCKONLY && RT == 1, "the staged form is the link-prefetch form with one right-hand side");
+        // FP64 input: in-block neighbours from the LDS copy of the block
+        // (stg), face neighbours from memory; the next hop's link one trip
+        // ahead as below
+        int bn, sn, sign;
+        bool inb;
+        neighbour_rt(a.g, b, bc, s, 0, +1, bn, sn, sign, inb);
+        cx<A> U[9];
+        load_hop_link<SF, A>(links, b, s, 0, bn, sn, a.r12, U);
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const vec2_t<SI> *p = in + ro[0] + ((long)bn * a.nrhs + r0) * 12 * BS + sn;
+            const A kk = (A)(-0.5 * sign);
+            int bn2 = bn, sn2 = sn, sign2 = sign;
+            bool inb2 = inb;
+            cx<A> Un[9];
+            if (k < 7) { // uniform
+                const int k2 = k + 1;
+                neighbour_rt(a.g, b, bc, s, k2 >> 1, (k2 & 1) ? -1 : 1, bn2, sn2, sign2, inb2);
+                load_hop_link<SF, A>(links, b, s, k2, bn2, sn2, a.r12, Un);
+            }
+            hop_stg_switch<SI, A>(k, p, stg, sn, inb, U, kk, acc[0]);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = Un[e];
+            bn = bn2;
+            sn = sn2;
+            sign = sign2;
+            inb = inb2;
+        }
+    } else if constexpr (PAIR && !BLOCKONLY && RT == 1 && sizeof(SI) <= 4) {
         // FP32 input, one right-hand side: both hops of a direction in one
         // trip, so the link that site x - mu reads for its forward hop is
         // re-read for the backward hop of site x at once (from L1) rather
@@ -257,8 +373,19 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         ro[rr] = (long)(r - r0) * 12 * BS + (a.in_off ? a.in_off[r] : 0);
         diag[rr] = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
     }
-    hops<BLOCKONLY, (sizeof(A) == 8 || sizeof(SI) == 2) && RT == 1, RT == 1 && sizeof(SI) == 4, RT, SI, SF, A>(
-        in, links, a, b, bc, r0, ro, s, acc);
+    // one right-hand side per workgroup: the block's input spinor is staged
+    // in LDS once (coalesced), and the in-block hops and the clover term read
+    // it from there; only face neighbours come from memory
+    constexpr bool STG = RT == 1 && G == 1 && !BLOCKONLY;
+    __shared__ vec2_t<SI> stg[STG ? 12 * BS : 1];
+    if constexpr (STG) {
+        const vec2_t<SI> *own = in + ro[0] + ((long)b * a.nrhs + r0) * 12 * BS + s;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) stg[c * BS + s] = own[c * BS];
+        __syncthreads();
+    }
+    hops<BLOCKONLY, (sizeof(A) == 8 || sizeof(SI) == 2) && RT == 1, RT == 1 && sizeof(SI) == 4, RT, SI, SF, A, STG>(
+        in, links, a, b, bc, r0, ro, s, acc, stg);
     // one chiral half at a time: halves the registers the clover needs
 #pragma unroll 1
     for (int k = 0; k < 2; ++k) {
@@ -271,7 +398,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DslashWaves<
         for (int rr = 0; rr < RT; ++rr) {
             const long sp = ((long)b * a.nrhs + r0) * 12 * BS + s + ro[rr];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) raw[rr][c] = in[sp + (6 * k + c) * BS];
+            for (int c = 0; c < 6; ++c) raw[rr][c] = STG ? stg[(6 * k + c) * BS + s] : in[sp + (6 * k + c) * BS];
         }
 #pragma unroll
         for (int rr = 0; rr < RT; ++rr) {

@@ -86,20 +86,22 @@ ProfScope::~ProfScope()
 
 namespace {
 
-// Streaming copy: 16-byte non-temporal loads and stores, four per thread in
-// flight, grid-stride; the achievable-HBM-bandwidth reference the kernels are
-// compared with.
+// Streaming copy: 16-byte non-temporal loads and stores, a tile of 1024
+// vectors per workgroup (four per thread, all loads issued before the
+// stores); the achievable-HBM-bandwidth reference the kernels are compared
+// with.
 __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
 {
-    const size_t stride = (size_t)gridDim.x * 256 * 4;
-    for (size_t i = ((size_t)blockIdx.x * 256 * 4) + threadIdx.x; i < n; i += stride) {
+    const size_t i = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i + 3 * 256 < n) {
         uint4 v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (i + k * 256 < n) v[k] = ld_stream(src + i + k * 256);
+        for (int k = 0; k < 4; ++k) v[k] = ld_stream(src + i + k * 256);
 #pragma unroll
+        for (int k = 0; k < 4; ++k) st_stream(dst + i + k * 256, v[k]);
+    } else {
         for (int k = 0; k < 4; ++k)
-            if (i + k * 256 < n) st_stream(dst + i + k * 256, v[k]);
+            if (i + k * 256 < n) st_stream(dst + i + k * 256, ld_stream(src + i + k * 256));
     }
 }
 
@@ -108,12 +110,9 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ s
 Status stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
 {
     const size_t n = bytes / 16;
-    int dev = 0, cus = 256;
-    DD_HIP_TRY(hipGetDevice(&dev));
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    const size_t want = (n + 1023) / 1024;
-    const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)cus * 8));
-    k_stream_copy<<<grid, 256, 0, st>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+    const size_t grid = (n + 1023) / 1024;
+    if (grid > 0x7fffffffu) return Status{DD_INVALID_ARG, "stream copy: too large"};
+    k_stream_copy<<<(unsigned)grid, 256, 0, st>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }

@@ -9,7 +9,7 @@
   direction, so every neighbour is distinct);
 * restriction and prolongation in FP64 and FP32;
 * the coarse solve (k GMRES steps) against the least-residual vector of the
-  Krylov space, on the FP32-rounded coarse operator the device applies;
+  Krylov space, on the FP16-rounded coarse operator the device applies;
 * the two-grid preconditioner against the oracle's, in FP64 and FP32;
 * SAP-FGMRES solves with the two-grid preconditioner, residual checked by
   the oracle's operator.
@@ -50,8 +50,11 @@ def dense_from_blocks(dims, A):
     return D
 
 
-def f32(z):
-    return z.real.astype(np.float32).astype(np.float64) + 1j * z.imag.astype(np.float32).astype(np.float64)
+def f16(z):
+    """The device's copy of D_c for the coarse solve: each real part rounded
+    to FP32, then to FP16, both to nearest even."""
+    r = lambda a: a.astype(np.float32).astype(np.float16).astype(np.float64)
+    return r(z.real) + 1j * r(z.imag)
 
 
 @pytest.fixture(scope="module")
@@ -119,11 +122,11 @@ def test_restrict_prolong(c1, prec, tol):
 
 def test_coarse_solve_is_the_krylov_minimiser(c1):
     """k = 8 GMRES steps on (D_c + m0) x = b for two right-hand sides with
-    their own masses; the device applies the FP32 copy of D_c."""
+    their own masses; the device applies the FP16 copy of D_c."""
     import torch
-    # the device rounds every block to FP32 and sums neighbours that coincide
+    # the device rounds every block to FP16 and sums neighbours that coincide
     # (two blocks per direction) in FP64
-    Dc = dense_from_blocks(c1.dims, f32(c1.Ad))
+    Dc = dense_from_blocks(c1.dims, f16(c1.Ad))
     nc = Dc.shape[0]
     rng = np.random.default_rng(74)
     b = rng.standard_normal((2, nc)) + 1j * rng.standard_normal((2, nc))
@@ -151,7 +154,7 @@ def test_coarse_solve_is_the_krylov_minimiser(c1):
 def test_two_grid_preconditioner(c1, prec, tol):
     import torch
     P = oracle_P(c1.P)
-    Dc = dense_from_blocks(c1.dims, f32(c1.Ad))
+    Dc = dense_from_blocks(c1.dims, f16(c1.Ad))
     tl = amg.TwoLevel(c1.dims, (4, 4, 4, 4), c1.U, c1.C, P, Dc, M0, k=8, nu=2, nmr=4, bc=BC)
     eta = synth.gaussian_spinor(c1.dims, seed=75)
     x = to_dev(eta)
@@ -209,7 +212,7 @@ def test_galerkin_identity_16x4():
     lat.ctx.synchronize()
     fine = oracle.apply_D(lat.dims, lat.U, lat.C, -0.25, amg.prolong(lat.dims, (4, 4, 4, 4), P, xc), BC)
     ref = amg.restrict(lat.dims, (4, 4, 4, 4), P, fine).reshape(-1)
-    assert rel(to_host(yc)[0], ref) < 1e-6  # the device applies the FP32 copy of D_c
+    assert rel(to_host(yc)[0], ref) < 2e-3  # the device applies the FP16 copy of D_c
     lat.ctx.close()
 
 
