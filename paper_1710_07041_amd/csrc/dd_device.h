@@ -28,7 +28,7 @@ constexpr int MAXRHS = 16;
 // complex numbers
 // ---------------------------------------------------------------------------
 template <typename A>
-struct cx {
+struct alignas(2 * sizeof(A)) cx {
     A re, im;
 };
 
