@@ -457,11 +457,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
         const vec2_t<SI> *__restrict__ inr = in + (a.in_off ? a.in_off[r] : 0);
         const long sp = ((long)b * a.nrhs + r) * 12 * BS + s;
+        // the hops that leave the block into the spare LDS buffer (the
+        // t-hop barrier inside block_apply publishes them)
+        face_hops_coop<SI, SF, A>(a.g, b, bc, s, r, a.nrhs, inr, links, a.r12, &L.hf[0][0][0], &L.hb[0][0][0]);
         cx<A> v[12], q[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = ldc<A>(inr + sp + c * BS);
         block_apply<SF, A, RES, NTC>(L, a.g, b, bc, s, U, cl, links, clov, diag, v, q);
-        face_hops<SI, SF, A, RES::links>(a.g, b, bc, s, r, a.nrhs, inr, links, U, q, a.r12);
+        face_gather(a.g, s, &L.hf[0][0][0], &L.hb[0][0][0], q);
         if (RESID) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) stc_stream(out + sp + c * BS, ldc_stream<A>(resid + sp + c * BS) - q[c]);

@@ -10,9 +10,10 @@ from paper_1710_07041_amd import synth
 pytestmark = pytest.mark.gpu
 
 # lattices: one block spanning everything (every hop wraps inside the block),
-# mixed one/two/four blocks per direction, and a 12-block lattice whose block
-# count is not a multiple of the eight XCDs (ragged workgroup remap)
-SHAPES = [(4, 4, 4, 4), (8, 4, 16, 8), (4, 4, 8, 24), (8, 8, 8, 8)]
+# mixed one/two/four blocks per direction, a 12-block lattice whose block
+# count is not a multiple of the eight XCDs (ragged workgroup remap), and
+# four blocks in x, y and z (forward and backward neighbour blocks distinct)
+SHAPES = [(4, 4, 4, 4), (8, 4, 16, 8), (4, 4, 8, 24), (8, 8, 8, 8), (16, 16, 16, 8)]
 
 
 @pytest.fixture(scope="module", params=SHAPES, ids=lambda d: "x".join(map(str, d)))
