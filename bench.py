@@ -95,6 +95,9 @@ def parse():
                     help="device memory for the right-hand sides and solutions of requests in flight")
     ap.add_argument("--serve-fp64-requests", type=int, default=48, help="requests of the FP64-path comparison")
     ap.add_argument("--no-standalone", action="store_true")
+    ap.add_argument("--standalone-only", default="",
+                    help="only time the operator alone for these cases (e.g. f64x1,f32x12) on the workload lattice, "
+                         "print them as one JSON line and stop (for counter runs of single operator forms)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="multi-RHS workloads: skip the one-at-a-time solves (e.g. for counter runs that should "
                          "see only fused launches)")
@@ -202,17 +205,19 @@ def roofline_entry(name, st, peak_gbs=HBM_PEAK_GBS):
             "frac_hbm": round(gbs / peak_gbs, 4)}
 
 
-def dslash_standalone(ctx, dims, reps=20, copy_gbs=None):
+def dslash_standalone(ctx, dims, reps=20, copy_gbs=None, cases=None):
     """The operator alone in every precision, for one and (up to 32^3x64) for
-    12 fused right-hand sides, timed with HIP events on the context stream:
-    GB/s vs the roofline (and vs the measured copy bandwidth)."""
+    12 fused right-hand sides (or the given (precision, nrhs) cases), timed
+    with HIP events on the context stream: GB/s vs the roofline (and vs the
+    measured copy bandwidth)."""
     import torch
     from paper_1710_07041_amd import synth
     res = {}
     V = synth.volume(dims)
-    cases = [("f64", 1), ("f32", 1), ("f16", 1)]
-    if V <= 32 ** 3 * 64:
-        cases += [("f64", 12), ("f32", 12), ("f16", 12)]
+    if cases is None:
+        cases = [("f64", 1), ("f32", 1), ("f16", 1)]
+        if V <= 32 ** 3 * 64:
+            cases += [("f64", 12), ("f32", 12), ("f16", 12)]
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     for prec, n in cases:
@@ -451,6 +456,12 @@ def main():
     del sa, sb
     torch.cuda.empty_cache()
     log(f"streaming copy: {copy_gbs:.0f} GB/s")
+
+    if args.standalone_only:
+        cases = [(c.split("x")[0], int(c.split("x")[1])) for c in args.standalone_only.split(",")]
+        res = dslash_standalone(ctx, dims, copy_gbs=copy_gbs, cases=cases)
+        print(json.dumps({"workload": w["text"], "hbm_copy_gbs": round(copy_gbs, 1), "operator_alone": res}))
+        return
 
     for i in range(args.warmup):
         info = one_solve(w["sap"])
