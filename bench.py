@@ -17,8 +17,9 @@ The JSON line reports
   value            algorithmic GB/s of the FP64 Wilson-clover operator launches
                    inside the timed solves (HIP events on the launch stream);
   roofline         the kernel class that dominates the step time, priced with
-                   the survey's algorithmic count (10,584 flops per site and
-                   SAP cycle), the kernel's own count beside it;
+                   the method's algorithmic count (10,584 flops per site and
+                   SAP cycle: four MR steps of 2,184 and a block residual of
+                   1,848), the kernel's own count beside it;
   roofline_dslash  the operator itself, against 8 TB/s HBM and against the
                    measured device-copy bandwidth;
   time_to_solution mixed vs the FP64 GPU path (median and min of the repeats);
@@ -604,7 +605,7 @@ def main():
     rdom = roofline_entry(dom, prof[dom])
     if dom.startswith("sap"):
         # smoother: arithmetic intensity above the FP32 ridge -> priced against
-        # the vector ALU peak.  Algorithmic work per launch: the survey's
+        # the vector ALU peak.  Algorithmic work per launch: the method's
         # count, 10,584 flops per site and SAP cycle (four MR steps of 2,184
         # and the block residual of 1,848), times the V/2 sites x nrhs one
         # colour sweep covers; the kernel's own count (the carried residual
