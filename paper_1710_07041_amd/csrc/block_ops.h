@@ -241,19 +241,31 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
 {
 #pragma unroll
     for (int c = 0; c < 12; ++c) q[c] = mk<A>(0, 0);
+    // FP16 fields: clover half 1 stays in flight as FP16 pairs across the
+    // in-block hops and is applied after them, so its L2 latency hides behind
+    // the hops (with FP32 fields the pending loads take twice the registers,
+    // and that form measured slower)
+    constexpr bool LATE = RES::clover_half && RES::links && sizeof(S) == 2;
+    vec2_t<S> c2late[LATE ? 18 : 1];
     if constexpr (RES::clover) {
         clover_mac(cl, diag, v, q);
     } else if constexpr (RES::clover_half) {
-        cx<A> c2[18];
         const vec2_t<S> *cp = clov_g + ((long)b * 36 + 18) * BS + s;
         // the address is the same at every MR step: hide that, or the loads
         // are hoisted out of the MR loop and the half is held in registers
         asm volatile("" : "+v"(cp));
-        // half 1's loads are in flight while half 0 (registers) is applied
+        if constexpr (LATE) {
 #pragma unroll
-        for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
-        clover_half_mac<A>(cl, diag, v, q);
-        clover_half_mac<A>(c2, diag, v + 6, q + 6);
+            for (int e = 0; e < 18; ++e) c2late[e] = cp[e * BS];
+            clover_half_mac<A>(cl, diag, v, q);
+        } else {
+            // half 1's loads are in flight while half 0 (registers) is applied
+            cx<A> c2[18];
+#pragma unroll
+            for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(cp + e * BS);
+            clover_half_mac<A>(cl, diag, v, q);
+            clover_half_mac<A>(c2, diag, v + 6, q + 6);
+        }
     } else {
 #pragma unroll 1
         for (int k = 0; k < 2; ++k) {
@@ -271,6 +283,12 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
         exchange_dir<1, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
         exchange_dir<2, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
         exchange_dir<3, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        if constexpr (LATE) {
+            cx<A> c2[18];
+#pragma unroll
+            for (int e = 0; e < 18; ++e) c2[e] = ldc<A>(&c2late[e]);
+            clover_half_mac<A>(c2, diag, v + 6, q + 6);
+        }
     } else {
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
