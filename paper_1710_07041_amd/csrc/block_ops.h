@@ -167,7 +167,11 @@ template <int MU, int DIR, typename A> __device__ __forceinline__ cx<A> lane_hop
 // neighbours carry the boundary sign only when the block spans the whole
 // direction (one block per direction); otherwise the reconstruction is a
 // plain sum.
-template <int MU, typename S, typename A, bool LANES>
+//
+// PHASE splits a direction that goes through LDS: 1 posts this site's half
+// spinors and returns, 2 waits at the barrier and takes the neighbours'
+// (0 does both), so that other work can sit between the two.
+template <int MU, typename S, typename A, bool LANES, int PHASE = 0>
 __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, const int bc[4], int s,
                                              const cx<A> U[9], const cx<A> v[12], cx<A> q[12])
 {
@@ -200,13 +204,16 @@ __device__ __forceinline__ void exchange_dir(Lds<A> &L, const Geom &g, int b, co
     }
     constexpr int X = MU & 1;
     cx<A> h[6], t[6];
-    proj_minus<MU>(v, h);
+    if constexpr (PHASE != 2) {
+        proj_minus<MU>(v, h);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) L.hf[X][c][s] = h[c];
-    proj_plus<MU>(v, h);
-    su3_mul_adj(U, h, t);
+        for (int c = 0; c < 6; ++c) L.hf[X][c][s] = h[c];
+        proj_plus<MU>(v, h);
+        su3_mul_adj(U, h, t);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) L.hb[X][c][s] = t[c];
+        for (int c = 0; c < 6; ++c) L.hb[X][c][s] = t[c];
+    }
+    if constexpr (PHASE == 1) return;
     __syncthreads();
     int bn, sn, sign;
     bool inb;
@@ -278,11 +285,22 @@ __device__ __forceinline__ void block_apply(Lds<A> &L, const Geom &g, int b, con
         }
     }
     if constexpr (RES::links) {
-        // links already in registers: no loads to hoist, unroll the directions
-        exchange_dir<0, S, A, LANES>(L, g, b, bc, s, Ur[0], v, q);
-        exchange_dir<1, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
-        exchange_dir<2, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
-        exchange_dir<3, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        // links already in registers: no loads to hoist, unroll the
+        // directions.  Across lanes, t alone goes through LDS: its half
+        // spinors are posted first and taken last, so the x, y and z hops
+        // run while the other wavefronts reach the barrier.
+        if constexpr (LANES) {
+            exchange_dir<3, S, A, LANES, 1>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+            exchange_dir<0, S, A, LANES>(L, g, b, bc, s, Ur[0], v, q);
+            exchange_dir<1, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
+            exchange_dir<2, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
+            exchange_dir<3, S, A, LANES, 2>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        } else {
+            exchange_dir<0, S, A, LANES>(L, g, b, bc, s, Ur[0], v, q);
+            exchange_dir<1, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 1 : 0], v, q);
+            exchange_dir<2, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 2 : 0], v, q);
+            exchange_dir<3, S, A, LANES>(L, g, b, bc, s, Ur[RES::links ? 3 : 0], v, q);
+        }
         if constexpr (LATE) {
             cx<A> c2[18];
 #pragma unroll
