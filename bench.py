@@ -161,6 +161,7 @@ def cpu_baseline(seconds, workload=None, full=False):
                              "params": "FGMRES(20), SAP ncy=12 nmr=4, m0=-0.2, eps=0.3, tol 1e-10"}}
     if full and workload is not None:
         wd = workload["dims"]
+        log(f"cpu baseline: the oracle on the workload lattice {wd}")
         Vw = synth.volume(wd)
         Uw = synth.random_su3_links(wd, workload["eps"], seed=0)
         Cw = oracle.clover_field(wd, Uw, workload["csw"])
@@ -175,6 +176,8 @@ def cpu_baseline(seconds, workload=None, full=False):
                                    "apply_gbs": round(Vw * 192 * 8 / dw / 1e9, 3),
                                    "sap_cycle_ms": round(sw * 1e3, 1)}
         del Uw, Cw, pw
+        log(f"cpu baseline: workload lattice apply {dw * 1e3:.0f} ms, one SAP cycle {sw:.1f} s; "
+            "now the full 32^3x64 oracle solve")
         d2 = (32, 32, 32, 64)
         U2 = synth.random_su3_links(d2, 0.5, seed=0)
         C2 = oracle.clover_field(d2, U2, 1.0)
