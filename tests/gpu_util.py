@@ -80,13 +80,14 @@ def to_host(t):
 class Lattice:
     """A gauge field resident on the GPU plus its oracle clover (for small volumes)."""
 
-    def __init__(self, dims, eps, csw=1.0, seed=0, oracle_clover=True):
+    def __init__(self, dims, eps, csw=1.0, seed=0, oracle_clover=True, bcs=BC):
         from paper_1710_07041_amd import ddsap
         self.dims = tuple(dims)
         self.V = synth.volume(dims)
         self.csw = csw
+        self.bcs = tuple(bcs)
         self.U = synth.random_su3_links(dims, eps, seed=seed)
-        self.ctx = ddsap.Context(dims, BC)
+        self.ctx = ddsap.Context(dims, self.bcs)
         self.ctx.set_gauge(self.U, csw)
         self.C = oracle.clover_field(dims, self.U, csw) if oracle_clover else None
 
