@@ -448,11 +448,13 @@ typedef struct {
     double flops;
 } dd_kernel_stat;
 
-/* Copy bytes (a multiple of 16) from src to dst (device pointers, not
- * overlapping) on stream with a plain streaming kernel: 16-byte
- * non-temporal loads and stores, grid-stride.  The achievable HBM bandwidth
- * it reaches (2 * bytes / time) is the reference line the operator and
- * smoother rates are compared with.  DD_INVALID_ARG for bad sizes. */
+/* Copy bytes (a multiple of 16, nonzero) from src to dst (device pointers,
+ * not overlapping) on stream with a plain streaming kernel: one workgroup
+ * per 16 KiB tile, each thread issuing four 16-byte non-temporal loads
+ * before its four stores (a partial last tile element by element).  The
+ * HBM bandwidth it reaches (2 * bytes / time) is the reference line the
+ * operator and smoother rates are compared with.  DD_INVALID_ARG for null
+ * pointers or bad sizes. */
 dd_status dd_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Switch event timing on (1) or off (0); switching on clears the counters. */
