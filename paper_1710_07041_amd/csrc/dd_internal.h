@@ -160,7 +160,9 @@ Status set_clover_canon(dd_ctx *ctx, const double *C_dev_canon);
 Status pack_spinor(dd_ctx *ctx, const double *canon, void *blocked, int prec, int nrhs);
 Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, int nrhs);
 // one FP64 right-hand side <-> slot `slot` of a `width`-wide blocked FP64 buffer
-Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot);
+// nonzero (device, optional): set to 1 if any entry of canon is nonzero
+Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot,
+                 int *nonzero = nullptr);
 Status unpack_slot(dd_ctx *ctx, hipStream_t st, const void *blocked, double *canon, int width, int slot);
 Status any_nonfinite(dd_ctx *ctx, const double *p, size_t n, bool &bad);
 

@@ -47,7 +47,11 @@ struct SlotState {
     // diagonal (the projected least-squares problem has no unique solution)
     bool singular(int m, int n) const;
     dd_solve_info info{};
-    long owner = 0; // caller's tag (request id) and right-hand-side index
+    // initial guess known to be zero (none given, or all entries zero as the
+    // packing pass found): the first residual is b, with no operator call
+    bool x0_zero = false;
+    bool x0_check = false; // the packing pass's verdict is still on the device
+    long owner = 0;        // caller's tag (request id) and right-hand-side index
     int owner_rhs = 0;
 };
 

@@ -520,6 +520,8 @@ struct Engine::Impl {
     long vlen = 0; // complex entries of one width-wide vector
     int G = 0;
     DevBuf V, Z, w, xb, bb, lp, sapout, sapscr, partial, res, res2, resb, y, scl, slots;
+    DevBuf xnz;           // per slot: the packed initial guess has a nonzero entry
+    int *h_xnz = nullptr; // its host copy (pinned)
     std::unique_ptr<AmgWork, AmgWorkDeleter> amgw; // the two-grid preconditioner's workspace
     SlotArrays *h_slots[3] = {nullptr, nullptr, nullptr}; // ring of pinned staging buffers
     int ring = 0;
@@ -537,6 +539,7 @@ struct Engine::Impl {
         if (h_res) (void)hipHostFree(h_res);
         if (h_resb) (void)hipHostFree(h_resb);
         if (h_y) (void)hipHostFree(h_y);
+        if (h_xnz) (void)hipHostFree(h_xnz);
         if (ev) (void)hipEventDestroy(ev);
     }
 
@@ -831,6 +834,8 @@ Status Engine::init(dd_ctx *ctx, const EngineParams &p)
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_res, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_resb, (size_t)e.W * KMAX * 16, hipHostMallocDefault));
     DD_HIP_TRY(hipHostMalloc((void **)&e.h_y, (size_t)e.W * ENGINE_MAXM * 16, hipHostMallocDefault));
+    DD_TRY(e.xnz.alloc((size_t)e.W * sizeof(int)));
+    DD_HIP_TRY(hipHostMalloc((void **)&e.h_xnz, (size_t)e.W * sizeof(int), hipHostMallocDefault));
     DD_HIP_TRY(hipEventCreateWithFlags(&e.ev, hipEventDisableTiming));
     e.S.assign(e.W, SlotState{});
     for (auto &s : e.S) {
@@ -862,9 +867,18 @@ Status Engine::admit(int r, const double *b_canon, const double *x0_canon, doubl
     Impl &e = *d;
     if (r < 0 || r >= e.W || e.S[r].state != SLOT_FREE) return Status{DD_INVALID_ARG, "engine: slot not free"};
     DD_TRY(pack_slot(e.ctx, e.st(), b_canon, e.bb.p, e.W, r));
+    SlotState &s0 = e.S[r];
     if (x0_canon) {
-        DD_TRY(pack_slot(e.ctx, e.st(), x0_canon, e.xb.p, e.W, r));
+        // the packing pass also finds whether x0 has a nonzero entry (the
+        // flag is cleared first; admission is never inside a captured graph)
+        int *flag = e.xnz.as<int>() + r;
+        DD_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), e.st()));
+        DD_TRY(pack_slot(e.ctx, e.st(), x0_canon, e.xb.p, e.W, r, flag));
+        s0.x0_zero = false;
+        s0.x0_check = true;
     } else {
+        s0.x0_zero = true;
+        s0.x0_check = false;
         // x0 = 0: clear slot r's chunk in every block (strided 2D clear,
         // never inside a captured graph)
         const size_t chunk = (size_t)12 * BS * 16;
@@ -908,6 +922,22 @@ Status Engine::launch_restart()
         bn |= s.state == SLOT_RESTART && s.need_bnorm;
     }
     if (!any) return Status::ok();
+    // whether freshly packed initial guesses were zero (one small copy and
+    // a wait, on the first restart of a slot given an x0 only)
+    bool check = false;
+    for (auto &s : e.S) check |= s.state == SLOT_RESTART && s.x0_check;
+    if (check) {
+        DD_HIP_TRY(hipMemcpyAsync(e.h_xnz, e.xnz.p, (size_t)e.W * sizeof(int), hipMemcpyDeviceToHost, e.st()));
+        DD_HIP_TRY(hipStreamSynchronize(e.st()));
+        for (int r = 0; r < e.W; ++r)
+            if (e.S[r].state == SLOT_RESTART && e.S[r].x0_check) {
+                e.S[r].x0_zero = e.h_xnz[r] == 0;
+                e.S[r].x0_check = false;
+            }
+    }
+    bool from_zero = true;
+    for (auto &s : e.S)
+        if (s.state == SLOT_RESTART) from_zero &= s.need_bnorm && s.x0_zero;
     SlotArrays &h = e.stage();
     e.fill_common(h);
     for (int r = 0; r < ENGINE_MAXW; ++r) {
@@ -918,6 +948,19 @@ Status Engine::launch_restart()
         h.eta_off[r] = h.psi_off[r] = h.in_off[r] = 0;
     }
     DD_TRY(e.upload(h));
+    if (from_zero) {
+        // every restarting slot starts from x0 = 0: r = b, so |r| = |b| and
+        // v_0 = b/|b| without an operator application
+        DD_TRY(e.update_dots(e.bb.as<double2>(), 0, nullptr));
+        DD_TRY(e.reduce(e.res.as<double2>(), 0));
+        DD_TRY(e.normalize(0, e.res.as<double2>(), e.bb.as<double2>()));
+        DD_HIP_TRY(hipMemcpyAsync(e.h_res, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+        DD_HIP_TRY(hipMemcpyAsync(e.h_resb, e.res.p, (size_t)e.W * KMAX * 16, hipMemcpyDeviceToHost, e.st()));
+        e.bnorm_pending = true;
+        DD_HIP_TRY(hipEventRecord(e.ev, e.st()));
+        e.restart_pending = true;
+        return Status::ok();
+    }
     if (bn) {
         // |b| of newly admitted slots
         DD_TRY(e.update_dots(e.bb.as<double2>(), 0, nullptr));

@@ -262,13 +262,20 @@ __global__ __launch_bounds__(TPB) void k_spinor_unpack(const vec2_t<S> *__restri
 
 // one canonical FP64 right-hand side <-> slot `slot` of a width-wide blocked buffer
 __global__ __launch_bounds__(TPB) void k_slot_pack(const double2 *__restrict__ in, double2 *__restrict__ out,
-                                                   CanonGeom g, int nblocks, int width, int slot)
+                                                   CanonGeom g, int nblocks, int width, int slot,
+                                                   int *__restrict__ nonzero)
 {
     int b = blockIdx.x, s = threadIdx.x;
     if (b >= nblocks) return;
     long x = canon_site(g, b, s);
     double2 *dst = out + ((long)b * width + slot) * 12 * BS + s;
-    for (int c = 0; c < 12; ++c) dst[(long)c * BS] = in[x * 12 + c];
+    bool nz = false;
+    for (int c = 0; c < 12; ++c) {
+        const double2 v = in[x * 12 + c];
+        nz |= v.x != 0.0 || v.y != 0.0; // NaN counts as nonzero
+        dst[(long)c * BS] = v;
+    }
+    if (nonzero && __any(nz) && (threadIdx.x % 64) == 0) atomicOr(nonzero, 1);
 }
 __global__ __launch_bounds__(TPB) void k_slot_unpack(const double2 *__restrict__ in, double2 *__restrict__ out,
                                                      CanonGeom g, int nblocks, int width, int slot)
@@ -392,12 +399,12 @@ Status unpack_spinor(dd_ctx *ctx, const void *blocked, double *canon, int prec, 
     return Status::ok();
 }
 
-Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot)
+Status pack_slot(dd_ctx *ctx, hipStream_t st, const double *canon, void *blocked, int width, int slot, int *nonzero)
 {
     const GeomHost &g = ctx->g;
     ProfScope ps(ctx->prof, st, K_PACK, (double)g.V * 24.0 * 16, 0.0);
     k_slot_pack<<<g.nblocks, TPB, 0, st>>>(reinterpret_cast<const double2 *>(canon), static_cast<double2 *>(blocked),
-                                           canon_geom(g), g.nblocks, width, slot);
+                                           canon_geom(g), g.nblocks, width, slot, nonzero);
     DD_HIP_TRY(hipGetLastError());
     return Status::ok();
 }

@@ -191,6 +191,27 @@ def test_solve_warm_start(c1):
     assert st == 0 and info[0]["iterations"] == 0
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_solve_initial_guess_with_one_nonzero_entry(c1, n):
+    """A solve that starts from zero takes r = b without applying the
+    operator; an initial guess with a single nonzero entry (in one of the
+    right-hand sides of a fused batch) must not be taken for zero: the
+    result then differs from b's solution by that guess unless D x0 enters
+    the first residual."""
+    from paper_1710_07041_amd import ddsap
+    b = synth.gaussian_spinor(c1.dims, nrhs=n, seed=12)
+    x0 = np.zeros_like(b)
+    x0[n - 1, 77, 2, 1] = 0.25 - 0.5j
+    bd, xd = to_dev(b), to_dev(x0)
+    m0 = np.full(n, -0.2)
+    st, info = c1.ctx.solve(m0, bd, xd, n, ddsap.default_params())
+    assert st == 0
+    x = xd.cpu().numpy()
+    for r in range(n):
+        res = b[r] - oracle.apply_D(c1.dims, c1.U, c1.C, -0.2, x[r], BC)
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10, r
+
+
 def test_fp16_range_fallback_to_fp32(c1):
     """The FP16 smoother's range safeguard: with every FP16 smoother output
     poisoned by an infinity (the host-side test hook), the FP16 path can
