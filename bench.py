@@ -95,6 +95,8 @@ def parse():
     ap.add_argument("--serve-hold-gb", type=int, default=48,
                     help="device memory for the right-hand sides and solutions of requests in flight")
     ap.add_argument("--serve-fp64-requests", type=int, default=48, help="requests of the FP64-path comparison")
+    ap.add_argument("--serve-prec", default="f32", choices=["f32", "f16"],
+                    help="storage precision of the serving smoother (FP32 arithmetic either way)")
     ap.add_argument("--no-standalone", action="store_true")
     ap.add_argument("--standalone-only", default="",
                     help="only time the operator alone for these cases (e.g. f64x1,f32x12) on the workload lattice, "
@@ -346,8 +348,8 @@ def serve_main(args):
                 "max_rel_residual": res, "submits_held_for_memory": capped}
 
     n = args.serve_requests
-    srv, fids, widths = make_server("f32")
-    log(f"mixed server: slots per field {widths}")
+    srv, fids, widths = make_server(args.serve_prec)
+    log(f"mixed server ({args.serve_prec} smoother): slots per field {widths}")
     sat = run(srv, fids, plan(7, n), inflight=args.serve_inflight)
     torch.cuda.empty_cache()
     log(f"saturation: {sat}")
@@ -376,7 +378,7 @@ def serve_main(args):
         "ms_per_step": round(1e3 * sat["wall_s"] / max(sat["requests"], 1), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "serving: resident 16^4, 24^3x48, 32^3x64 (eps=0.5, csw=1), m0~U[-0.38,-0.2], "
-                               "1-12 Gaussian RHS per request, SAP FP32 + FGMRES(20) FP64 to 1e-10, "
+                               f"1-12 Gaussian RHS per request, SAP {args.serve_prec.upper()} + FGMRES(20) FP64 to 1e-10, "
                                f"{n} requests per phase, HBM budget {args.serve_budget_gb} GB",
                    "slots_per_field": widths, "saturation_inflight": args.serve_inflight,
                    **({"sap_half_fields": True} if args.sap_half_fields else {})},

@@ -54,12 +54,14 @@ def make_requests(fields, n, seed=0):
     return reqs
 
 
-@pytest.mark.parametrize("graphs,eo,half", [(1, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1)],
-                         ids=["graphs", "nographs", "graphs-evenodd", "graphs-halffields"])
-def test_serve_mix_equals_alone(fields, graphs, eo, half):
+@pytest.mark.parametrize("graphs,eo,half,sap", [(1, 0, 0, "f32"), (0, 0, 0, "f32"), (1, 1, 0, "f32"),
+                                                  (1, 0, 1, "f32"), (1, 0, 0, "f16")],
+                         ids=["graphs", "nographs", "graphs-evenodd", "graphs-halffields", "graphs-fp16"])
+def test_serve_mix_equals_alone(fields, graphs, eo, half, sap):
     import torch
     from paper_1710_07041_amd import ddsap
-    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30, sap_eo=eo, sap_half_fields=half)
+    srv = ddsap.Server(max_width=3, use_graphs=graphs, hbm_budget_bytes=8 << 30, sap_eo=eo, sap_half_fields=half,
+                       sap_prec=sap)
     fids = [srv.add_field(dims, U, 1.0, BC) for dims, U, _ in fields]
     for f in fids:
         assert srv.field_info(f)[0] == 3
@@ -87,7 +89,7 @@ def test_serve_mix_equals_alone(fields, graphs, eo, half):
         for r in range(b.shape[0]):
             res = b[r] - oracle.apply_D(dims, U, C, m0[r], x[r], BC)
             assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-10
-        xs = solo(dims, U, m0, b, eo=eo, half=half)
+        xs = solo(dims, U, m0, b, sap=sap, eo=eo, half=half)
         assert rel(x, xs) <= 1e-8
 
 
