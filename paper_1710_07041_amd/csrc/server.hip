@@ -27,6 +27,7 @@
 
 #include "dd_internal.h"
 #include "engine.h"
+#include "serve_core.h"
 
 struct dd_server {
     dd_server_config cfg{};
@@ -39,35 +40,16 @@ struct dd_server {
         std::vector<std::pair<long, int>> slot_owner; // (request, rhs) per slot
     };
     std::vector<Field> fields;
-    struct Request {
-        long id = 0;
-        int field = 0;
-        int nrhs = 0;
-        std::vector<double> m0;
-        const double *b = nullptr;
-        double *x = nullptr;
-        int next_rhs = 0; // next right-hand side to admit
-        int done_rhs = 0;
-        std::vector<dd_solve_info> info;
-        double t_submit = 0, t_admit = -1, t_done = 0;
-        bool complete = false;
-        int status = DD_OK;
-    };
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<long> queue;
-    std::unordered_map<long, Request> reqs;
-    long next_id = 1;
+    dd::ServeQueue q; // requests, admission order, completion accounting (under mu)
     std::vector<std::thread> workers; // one per field
     std::atomic<bool> stop{false};
     bool started = false;
     size_t used = 0;
     std::string err;
     int fatal = DD_OK;
-    // statistics
-    std::vector<double> latencies_ms;
-    long rhs_done = 0, iterations = 0;
-    double t_first = -1, t_last = 0, busy_s = 0;
+    double busy_s = 0;
 };
 
 namespace {
@@ -78,55 +60,18 @@ double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-double percentile(std::vector<double> v, double q)
-{
-    if (v.empty()) return 0.0;
-    std::sort(v.begin(), v.end());
-    double pos = q * (v.size() - 1);
-    size_t lo = (size_t)pos;
-    size_t hi = std::min(lo + 1, v.size() - 1);
-    double f = pos - lo;
-    return v[lo] * (1 - f) + v[hi] * f;
-}
-
 // One pass of field fi's worker: admit its queued right-hand sides, run one
 // engine iteration if any slot is busy, harvest finished right-hand sides.
 dd::Status work_once(dd_server *s, int fi, bool &did_work)
 {
     did_work = false;
     dd_server::Field &f = s->fields[fi];
-    struct Adm {
-        int slot;
-        long req;
-        int rhs;
-        const double *b;
-        double m0;
-    };
-    std::vector<Adm> adm;
+    std::vector<dd::ServeAdmit> adm;
+    const size_t vstride = (size_t)f.ctx->g.V * 24;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        for (auto it = s->queue.begin(); it != s->queue.end();) {
-            dd_server::Request &r = s->reqs[*it];
-            if (r.field != fi) {
-                ++it;
-                continue;
-            }
-            while (r.next_rhs < r.nrhs) {
-                // a slot is taken when the engine has it free and no admission
-                // of this pass has reserved it yet
-                int slot = -1;
-                for (int k = 0; k < f.eng->width() && slot < 0; ++k)
-                    if (f.eng->slot(k).state == dd::SLOT_FREE && f.slot_owner[k].first == 0) slot = k;
-                if (slot < 0) break;
-                f.slot_owner[slot] = {r.id, r.next_rhs};
-                const size_t vstride = (size_t)f.ctx->g.V * 24;
-                adm.push_back({slot, r.id, r.next_rhs, r.b + r.next_rhs * vstride, r.m0[r.next_rhs]});
-                if (r.t_admit < 0) r.t_admit = now_s();
-                ++r.next_rhs;
-            }
-            if (r.next_rhs == r.nrhs) it = s->queue.erase(it);
-            else ++it;
-        }
+        s->q.admit(
+            fi, [&](int k) { return f.eng->slot(k).state == dd::SLOT_FREE; }, f.slot_owner, vstride, now_s(), adm);
     }
     for (auto &a : adm) DD_TRY(f.eng->admit(a.slot, a.b, nullptr, a.m0, a.req, a.rhs));
     if (f.eng->busy_slots() == 0) return dd::Status::ok();
@@ -137,22 +82,16 @@ dd::Status work_once(dd_server *s, int fi, bool &did_work)
     if (f.eng->busy_slots()) DD_TRY(f.eng->launch_step());
     DD_TRY(f.eng->finish_step());
     // harvest finished right-hand sides
-    struct Fin {
-        long req;
-        int rhs;
-        dd_solve_info info;
-    };
-    std::vector<Fin> fin;
+    std::vector<dd::ServeDone> fin;
     for (int r = 0; r < f.eng->width(); ++r) {
         dd::SlotState &st = f.eng->slot(r);
         if (st.state != dd::SLOT_DONE) continue;
-        long req = f.slot_owner[r].first;
-        int rhs = f.slot_owner[r].second;
+        const long req = f.slot_owner[r].first;
+        const int rhs = f.slot_owner[r].second;
         double *xdst = nullptr;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            auto it = s->reqs.find(req);
-            if (it != s->reqs.end()) xdst = it->second.x + (size_t)rhs * f.ctx->g.V * 24;
+            xdst = s->q.result(req, rhs, vstride);
         }
         if (xdst) DD_TRY(f.eng->extract(r, xdst));
         fin.push_back({req, rhs, st.info});
@@ -163,21 +102,7 @@ dd::Status work_once(dd_server *s, int fi, bool &did_work)
     const double t1 = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     s->busy_s += t1 - t0;
-    for (auto &fi2 : fin) {
-        auto it = s->reqs.find(fi2.req);
-        if (it == s->reqs.end()) continue;
-        dd_server::Request &r = it->second;
-        r.info[fi2.rhs] = fi2.info;
-        if (fi2.info.status != DD_OK && r.status == DD_OK) r.status = fi2.info.status;
-        s->iterations += fi2.info.iterations;
-        ++s->rhs_done;
-        if (++r.done_rhs == r.nrhs) {
-            r.complete = true;
-            r.t_done = t1;
-            s->latencies_ms.push_back((r.t_done - r.t_submit) * 1e3);
-            s->t_last = t1;
-        }
-    }
+    s->q.finish(fin, t1);
     if (!fin.empty()) s->cv_done.notify_all();
     return dd::Status::ok();
 }
@@ -198,12 +123,7 @@ void worker_main(dd_server *s, int fi)
             std::lock_guard<std::mutex> lk(s->mu);
             s->fatal = st.code;
             s->err = "server: " + st.msg;
-            for (auto &kv : s->reqs)
-                if (!kv.second.complete) {
-                    kv.second.complete = true;
-                    kv.second.status = st.code;
-                }
-            s->queue.clear();
+            s->q.fail_all(st.code);
             s->stop.store(true);
             s->cv_done.notify_all();
             s->cv_work.notify_all();
@@ -212,7 +132,7 @@ void worker_main(dd_server *s, int fi)
         if (!did) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2),
-                                [&] { return s->stop.load() || !s->queue.empty(); });
+                                [&] { return s->stop.load() || !s->q.queue.empty(); });
         }
     }
 }
@@ -361,19 +281,7 @@ dd_status dd_server_submit(dd_server *s, int field_id, int nrhs, const double *m
             return DD_HIP_ERROR;
         }
     }
-    dd_server::Request r;
-    r.id = s->next_id++;
-    r.field = field_id;
-    r.nrhs = nrhs;
-    r.m0.assign(m0, m0 + nrhs);
-    r.b = b;
-    r.x = x;
-    r.info.assign(nrhs, dd_solve_info{});
-    r.t_submit = now_s();
-    if (s->t_first < 0) s->t_first = r.t_submit;
-    *request_id = r.id;
-    s->queue.push_back(r.id);
-    s->reqs.emplace(r.id, std::move(r));
+    *request_id = s->q.submit(field_id, nrhs, m0, b, x, now_s());
     s->cv_work.notify_all();
     return DD_OK;
 }
@@ -383,13 +291,7 @@ namespace {
 // holds s->mu).
 dd_status deliver(dd_server *s, long request_id, dd_solve_info *info, double *latency_ms)
 {
-    auto it = s->reqs.find(request_id);
-    const dd_server::Request &r = it->second;
-    if (info) std::memcpy(info, r.info.data(), sizeof(dd_solve_info) * r.nrhs);
-    if (latency_ms) *latency_ms = (r.t_done - r.t_submit) * 1e3;
-    const dd_status st = (dd_status)r.status;
-    s->reqs.erase(it);
-    return st;
+    return (dd_status)s->q.take(request_id, info, latency_ms);
 }
 } // namespace
 
@@ -397,8 +299,8 @@ dd_status dd_server_poll(dd_server *s, long request_id, int *done, dd_solve_info
 {
     if (!s || !done) return DD_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(request_id);
-    if (it == s->reqs.end()) return DD_INVALID_ARG;
+    auto it = s->q.reqs.find(request_id);
+    if (it == s->q.reqs.end()) return DD_INVALID_ARG;
     *done = it->second.complete ? 1 : 0;
     if (it->second.complete) return deliver(s, request_id, info, latency_ms);
     return DD_OK;
@@ -408,11 +310,11 @@ dd_status dd_server_wait(dd_server *s, long request_id, dd_solve_info *info, dou
 {
     if (!s) return DD_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(request_id);
-    if (it == s->reqs.end()) return DD_INVALID_ARG;
+    auto it = s->q.reqs.find(request_id);
+    if (it == s->q.reqs.end()) return DD_INVALID_ARG;
     // an element reference survives the rehash that a concurrent submit may
     // cause; an iterator does not
-    const dd_server::Request &r = it->second;
+    const dd::ServeRequest &r = it->second;
     s->cv_done.wait(lk, [&] { return r.complete; });
     return deliver(s, request_id, info, latency_ms);
 }
@@ -422,16 +324,17 @@ dd_status dd_server_get_stats(dd_server *s, dd_server_stats *out)
     if (!s || !out) return DD_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     std::memset(out, 0, sizeof(*out));
-    out->requests_done = (long)s->latencies_ms.size();
-    out->rhs_done = s->rhs_done;
-    out->iterations = s->iterations;
-    out->p50_ms = percentile(s->latencies_ms, 0.50);
-    out->p99_ms = percentile(s->latencies_ms, 0.99);
+    const dd::ServeQueue &q = s->q;
+    out->requests_done = (long)q.latencies_ms.size();
+    out->rhs_done = q.rhs_done;
+    out->iterations = q.iterations;
+    out->p50_ms = dd::ServeQueue::percentile(q.latencies_ms, 0.50);
+    out->p99_ms = dd::ServeQueue::percentile(q.latencies_ms, 0.99);
     double sum = 0;
-    for (double l : s->latencies_ms) sum += l;
-    out->mean_ms = s->latencies_ms.empty() ? 0 : sum / s->latencies_ms.size();
-    out->wall_s = s->t_first < 0 ? 0 : s->t_last - s->t_first;
-    out->rhs_per_s = out->wall_s > 0 ? s->rhs_done / out->wall_s : 0;
+    for (double l : q.latencies_ms) sum += l;
+    out->mean_ms = q.latencies_ms.empty() ? 0 : sum / q.latencies_ms.size();
+    out->wall_s = q.t_first < 0 ? 0 : q.t_last - q.t_first;
+    out->rhs_per_s = out->wall_s > 0 ? q.rhs_done / out->wall_s : 0;
     out->busy_s = s->busy_s;
     out->workspace_bytes = s->used;
     return DD_OK;
