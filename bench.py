@@ -626,6 +626,15 @@ def main():
                 "kernel_flops_per_launch": rdom["flops_per_launch"],
                 "hbm_gbs": rdom["gbs"], "hbm_frac": rdom["frac_hbm"], "avg_ms": rdom["avg_ms"],
                 "launches": rdom["launches"]}
+        # a visit's memory phase (fields, psi, residual and faces in and out)
+        # and its MR steps follow each other in a workgroup and, measured, do
+        # not overlap across the workgroups of a CU: the sum of the HBM time
+        # of the algorithmic bytes and the ALU time of the algorithmic flops
+        # is the floor of this structure
+        add_ms = (prof[dom]["bytes"] / prof[dom]["launches"] / (HBM_PEAK_GBS * 1e9)
+                  + alg_flops / (peak * 1e12)) * 1e3
+        roof["additive_bound_ms"] = round(add_ms, 4)
+        roof["frac_additive"] = round(add_ms / rdom["avg_ms"], 4)
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": rdom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": rdom["frac_hbm"], "traffic": None, "avg_ms": rdom["avg_ms"]}
