@@ -50,7 +50,7 @@ struct SlotState {
     // initial guess known to be zero (none given, or all entries zero as the
     // packing pass found): the first residual is b, with no operator call
     bool x0_zero = false;
-    bool x0_check = false; // the packing pass's verdict is still on the device
+    bool x0_check = false; // the packing pass's nonzero flag is still on the device
     long owner = 0;        // caller's tag (request id) and right-hand-side index
     int owner_rhs = 0;
 };
