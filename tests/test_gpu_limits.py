@@ -1,0 +1,87 @@
+"""The largest fused batch, sixteen right-hand sides each with its own mass,
+through the operator, the smoother and the solver, against the oracle; batch
+sizes outside 1..16 are rejected at the boundary before any work."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import BC, REL_TOL_APPLY, Lattice, check_sap, gpu_sap, rel, to_dev, to_host
+from paper_1710_07041_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NMAX = 16  # DD_MAX_RHS
+DIMS = (8, 4, 8, 8)  # blocks per direction 2, 1, 2, 2
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return Lattice(DIMS, eps=0.4, seed=31)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return synth.gaussian_spinor(DIMS, nrhs=NMAX, seed=32), np.linspace(-0.3, 0.25, NMAX)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_operator_sixteen(lat, batch, prec):
+    psi, m0 = batch
+    out = lat.apply(psi, m0, prec, nrhs=NMAX)
+    for r in range(NMAX):
+        ref = oracle.apply_D(DIMS, lat.U, lat.C, m0[r], psi[r], BC)
+        assert rel(out[r], ref) <= REL_TOL_APPLY[prec], r
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_sixteen(lat, batch, prec):
+    psi, m0 = batch
+    out = gpu_sap(lat.ctx, psi, m0, 3, 4, prec, nrhs=NMAX)
+    for r in (0, 7, NMAX - 1):
+        ref = oracle.sap(DIMS, (4, 4, 4, 4), lat.U, lat.C, m0[r], psi[r], 3, 4, BC)
+        check_sap(out[r], ref, prec, f"sixteen r={r}")
+    # the last slot of a full batch runs the instruction sequence of a lone
+    # right-hand side
+    assert np.array_equal(out[NMAX - 1], gpu_sap(lat.ctx, psi[NMAX - 1], m0[NMAX - 1], 3, 4, prec))
+
+
+@pytest.mark.parametrize("sap", ["f32", "f16"])
+def test_solve_sixteen(lat, batch, sap):
+    import torch
+    from paper_1710_07041_amd import ddsap
+    psi, m0 = batch
+    bd = to_dev(psi)
+    xd = torch.zeros_like(bd)
+    p = ddsap.default_params()
+    p.sap_prec = ddsap.PREC[sap]
+    st, info = lat.ctx.solve(m0, bd, xd, NMAX, p)
+    assert st == ddsap.DD_OK
+    x = to_host(xd)
+    for r in range(NMAX):
+        assert info[r]["status"] == ddsap.DD_OK
+        res = psi[r] - oracle.apply_D(DIMS, lat.U, lat.C, m0[r], x[r], BC)
+        assert np.linalg.norm(res) / np.linalg.norm(psi[r]) <= 1e-10, r
+
+
+def test_batch_size_limits(lat, batch):
+    """Zero or seventeen right-hand sides: DD_INVALID_ARG from the operator,
+    the smoother and the solver (the buffers hold sixteen and are not
+    touched)."""
+    import torch
+    from paper_1710_07041_amd import ddsap
+    psi, _ = batch
+    xb = lat.ctx.empty_blocked("f32", NMAX)
+    yb = lat.ctx.empty_blocked("f32", NMAX)
+    bd = to_dev(psi)
+    xd = torch.zeros_like(bd)
+    for n in (0, NMAX + 1):
+        m0 = np.zeros(max(n, 1))
+        with pytest.raises(ddsap.DDError) as e:
+            lat.ctx.apply_D(m0, xb, yb, "f32", n)
+        assert e.value.status == ddsap.DD_INVALID_ARG
+        with pytest.raises(ddsap.DDError) as e:
+            lat.ctx.sap(m0, xb, yb, 2, 4, "f32", n)
+        assert e.value.status == ddsap.DD_INVALID_ARG
+        st, _ = lat.ctx.solve(m0, bd, xd, n, ddsap.default_params(), raise_on_fail=False)
+        assert st == ddsap.DD_INVALID_ARG
+    assert float(torch.max(torch.abs(xd))) == 0.0
