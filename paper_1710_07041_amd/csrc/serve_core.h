@@ -85,7 +85,12 @@ class ServeQueue {
                std::vector<ServeAdmit> &out)
     {
         for (auto it = queue.begin(); it != queue.end();) {
-            ServeRequest &r = reqs[*it];
+            auto found = reqs.find(*it);
+            if (found == reqs.end()) { // forgotten (cannot happen while queued; kept safe)
+                it = queue.erase(it);
+                continue;
+            }
+            ServeRequest &r = found->second;
             if (r.field != fi) {
                 ++it;
                 continue;
@@ -142,10 +147,12 @@ class ServeQueue {
     }
 
     // Hand over completed request id (info: nrhs entries, may be NULL;
-    // latency_ms may be NULL) and forget it; returns its status.
+    // latency_ms may be NULL) and forget it; returns its status
+    // (DD_INVALID_ARG for an unknown id).
     int take(long id, dd_solve_info *info, double *latency_ms)
     {
         auto it = reqs.find(id);
+        if (it == reqs.end()) return DD_INVALID_ARG;
         const ServeRequest &r = it->second;
         if (info) std::copy(r.info.begin(), r.info.end(), info);
         if (latency_ms) *latency_ms = (r.t_done - r.t_submit) * 1e3;
