@@ -55,8 +55,9 @@ def make_requests(fields, n, seed=0):
 
 
 @pytest.mark.parametrize("graphs,eo,half,sap", [(1, 0, 0, "f32"), (0, 0, 0, "f32"), (1, 1, 0, "f32"),
-                                                  (1, 0, 1, "f32"), (1, 0, 0, "f16")],
-                         ids=["graphs", "nographs", "graphs-evenodd", "graphs-halffields", "graphs-fp16"])
+                                                  (1, 0, 1, "f32"), (1, 0, 0, "f16"), (1, 0, 0, "f64")],
+                         ids=["graphs", "nographs", "graphs-evenodd", "graphs-halffields", "graphs-fp16",
+                              "graphs-fp64"])
 def test_serve_mix_equals_alone(fields, graphs, eo, half, sap):
     import torch
     from paper_1710_07041_amd import ddsap
