@@ -450,8 +450,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RES::waves))
         for (int e = 0; e < (RES::clover ? 36 : 1); ++e) cl[e] = ldc<A>(cp + e * BS);
     }
     for (int r = 0; r < a.nrhs; ++r) {
-        // the t hop of the previous right-hand side may still be read from
-        // the LDS buffer that this one's t hop is about to overwrite
+        // the previous right-hand side's t hop and face gathers may still
+        // read the LDS buffers that this one's writes are about to overwrite
         __syncthreads();
         if (a.active && !a.active[r]) continue; // uniform over the workgroup
         const A diag = (A)(4.0 + (a.m0_dev ? a.m0_dev[r] : a.m0[r]));
