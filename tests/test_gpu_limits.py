@@ -1,6 +1,8 @@
-"""The largest fused batch, sixteen right-hand sides each with its own mass,
-through the operator, the smoother and the solver, against the oracle; batch
-sizes outside 1..16 are rejected at the boundary before any work."""
+"""Limits and degenerate inputs: the largest fused batch, sixteen right-hand
+sides each with its own mass, through the operator, the smoother and the
+solver, against the oracle; batch sizes outside 1..16 rejected at the
+boundary before any work; and the smoother on right-hand sides that vanish
+on some blocks (the block MR then meets <q, q> = 0 and stops) or entirely."""
 import numpy as np
 import pytest
 
@@ -85,3 +87,37 @@ def test_batch_size_limits(lat, batch):
         st, _ = lat.ctx.solve(m0, bd, xd, n, ddsap.default_params(), raise_on_fail=False)
         assert st == ddsap.DD_INVALID_ARG
     assert float(torch.max(torch.abs(xd))) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_blocks_with_zero_rhs(lat, prec):
+    """eta vanishes on two blocks (one of each colour): on the first visit
+    their residual is zero, the MR step finds <q, q> = 0 and stops with
+    delta = 0; later visits see the neighbours' updates.  The result matches
+    the oracle's SAP, which takes the same exit."""
+    from dense_ref import block_sites
+    eta = synth.gaussian_spinor(DIMS, seed=33)
+    colours = set()
+    for bid in (0, 1):
+        sites, col = block_sites(DIMS, (4, 4, 4, 4), bid)
+        colours.add(col)
+        eta[sites] = 0
+    assert colours == {0, 1}
+    out = gpu_sap(lat.ctx, eta, -0.2, 3, 4, prec)
+    ref = oracle.sap(DIMS, (4, 4, 4, 4), lat.U, lat.C, -0.2, eta, 3, 4, BC)
+    assert np.all(np.isfinite(out))
+    check_sap(out, ref, prec, "zero blocks")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_zero_rhs_in_batch(lat, prec):
+    """A batch whose middle right-hand side is zero: that one stays exactly
+    zero (every block stops at its first MR step), the others equal their
+    lone runs bitwise."""
+    eta = synth.gaussian_spinor(DIMS, nrhs=3, seed=34)
+    eta[1] = 0
+    m0 = np.array([-0.3, -0.2, -0.1])
+    out = gpu_sap(lat.ctx, eta, m0, 3, 4, prec, nrhs=3)
+    assert np.all(out[1] == 0)
+    for r in (0, 2):
+        assert np.array_equal(out[r], gpu_sap(lat.ctx, eta[r], m0[r], 3, 4, prec))
