@@ -307,6 +307,7 @@ dd_status dd_apply_D(dd_ctx *ctx, const double *m0, const void *x, void *y, int 
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_apply_D: non-finite mass");
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
+        dd::TraceRange tr("dd_apply_D");
         return dd::launch_dslash(ctx, m0, nrhs, x, prec, y, prec, prec, nullptr);
     });
 }
@@ -334,6 +335,7 @@ dd_status dd_sap(dd_ctx *ctx, const double *m0, const void *eta, void *psi, int 
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap: non-finite mass");
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
+        dd::TraceRange tr("dd_sap");
         return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec);
     });
 }
@@ -348,6 +350,7 @@ dd_status dd_sap_eo(dd_ctx *ctx, const double *m0, const void *eta, void *psi, i
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap_eo: non-finite mass");
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
+        dd::TraceRange tr("dd_sap_eo");
         return dd::run_sap(ctx, m0, nrhs, eta, psi, ncy, nmr, prec, nullptr, true);
     });
 }
@@ -363,6 +366,7 @@ dd_status dd_sap_noalloc(dd_ctx *ctx, const double *m0, const void *eta, void *p
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_sap_noalloc: non-finite mass");
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
+        dd::TraceRange tr("dd_sap_noalloc");
         return dd::run_sap_noalloc(ctx, m0, nrhs, eta, psi, ncy, nmr, prec);
     });
 }
@@ -386,6 +390,7 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_solve: non-finite mass");
     return guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
+        dd::TraceRange tr("dd_solve");
         return dd::solve(ctx, m0, b, x, nrhs, p, info);
     });
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <memory>
 #include <string>
@@ -11,6 +12,15 @@
 #include "../../include/ddsap.h"
 
 namespace dd {
+
+// A named range on the host timeline around one library call or one phase of
+// the solver (shown by rocprofv3 --marker-trace; a no-op without a tool).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 constexpr int BS_HOST = 256; // sites per 4^4 Schwarz block
 

@@ -1199,8 +1199,12 @@ Status Engine::finish_step()
 
 Status Engine::iterate()
 {
-    DD_TRY(launch_restart());
-    DD_TRY(finish_restart());
+    {
+        TraceRange tr("restart");
+        DD_TRY(launch_restart());
+        DD_TRY(finish_restart());
+    }
+    TraceRange tr("arnoldi_step");
     DD_TRY(launch_step());
     DD_TRY(finish_step());
     return Status::ok();

@@ -704,6 +704,7 @@ Status run_sap(dd_ctx *ctx, const double *m0, int nrhs, const void *eta, void *p
     void *faces = scratch;
     void *resid = static_cast<char *>(scratch) + spinor_bytes(ctx->g, prec, nrhs);
     const bool quiet = slots && slots->quiet;
+    TraceRange tr(eo ? "sap_eo" : "sap");
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             if (ctx->ncolour[col] == 0) continue;

@@ -76,6 +76,7 @@ dd::Status work_once(dd_server *s, int fi, bool &did_work)
     for (auto &a : adm) DD_TRY(f.eng->admit(a.slot, a.b, nullptr, a.m0, a.req, a.rhs));
     if (f.eng->busy_slots() == 0) return dd::Status::ok();
     did_work = true;
+    dd::TraceRange tr("serve_step");
     const double t0 = now_s();
     DD_TRY(f.eng->launch_restart());
     DD_TRY(f.eng->finish_restart());
