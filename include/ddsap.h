@@ -49,10 +49,14 @@
  * without waiting unless stated; device faults surface at the next
  * synchronising call.  One context serves one host thread at a time.
  *
- * Errors: every call returns a dd_status.  The library never aborts, never
- * throws across this boundary and never prints; dd_last_error gives the
- * message of the last failure on a context (or of the last failed dd_create
- * when passed NULL).
+ * Errors: every call returns a dd_status.  The library never aborts and
+ * never throws across this boundary; dd_last_error gives the message of the
+ * last failure on a context (or of the last failed dd_create when passed
+ * NULL).  It prints nothing unless the environment variable DDSAP_LOG is 1
+ * or more when the library first checks it: then every failed call and
+ * every dd_solve (per right-hand side: status, iterations, restarts,
+ * smoother calls, residual; and the call's wall time) write one line each
+ * to stderr.
  */
 #ifndef DDSAP_H
 #define DDSAP_H

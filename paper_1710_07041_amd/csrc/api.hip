@@ -1,7 +1,10 @@
 // C ABI of libddsap (declarations and contracts in include/ddsap.h).  Every
 // entry point validates its arguments, converts internal failures into a
 // dd_status plus a message, and never lets a C++ exception cross the boundary.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -24,9 +27,21 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Diagnostics on stderr, off unless DDSAP_LOG is set (read once): 1 prints a
+// line per failed call and per solve (iterations, residual, wall time).
+int log_level()
+{
+    static const int level = [] {
+        const char *e = std::getenv("DDSAP_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return level;
+}
+
 dd_status fail(dd_ctx *ctx, const dd::Status &s)
 {
     if (ctx) ctx->err = s.msg;
+    if (log_level() >= 1) std::fprintf(stderr, "[ddsap] error %d: %s\n", (int)s.code, s.msg.c_str());
     return s.code;
 }
 
@@ -388,11 +403,23 @@ dd_status dd_solve(dd_ctx *ctx, const double *m0, const double *b, double *x, in
     if (!ctx->has_field) return fail(ctx, DD_NO_FIELD, "dd_solve: no gauge field");
     for (int r = 0; r < nrhs; ++r)
         if (!std::isfinite(m0[r])) return fail(ctx, DD_INVALID_ARG, "dd_solve: non-finite mass");
-    return guarded(ctx, [&]() -> dd::Status {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<dd_solve_info> own(log_level() >= 1 && !info ? nrhs : 0);
+    dd_solve_info *inf = info ? info : (own.empty() ? nullptr : own.data());
+    const dd_status st = guarded(ctx, [&]() -> dd::Status {
         DD_TRY(set_device(ctx));
         dd::TraceRange tr("dd_solve");
-        return dd::solve(ctx, m0, b, x, nrhs, p, info);
+        return dd::solve(ctx, m0, b, x, nrhs, p, inf);
     });
+    if (log_level() >= 1 && inf) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[ddsap] dd_solve: %d right-hand side(s), status %d, %.3f ms\n", nrhs, (int)st, ms);
+        for (int r = 0; r < nrhs; ++r)
+            std::fprintf(stderr, "[ddsap]   rhs %d: status %d, %d iterations, %d restarts, %d smoother calls, "
+                                 "residual %.3e\n",
+                         r, inf[r].status, inf[r].iterations, inf[r].restarts, inf[r].sap_calls, inf[r].rel_residual);
+    }
+    return st;
 }
 
 dd_status dd_amg_setup(dd_ctx *ctx, double m0, const double *v0, const dd_amg_params *p)
