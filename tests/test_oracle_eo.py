@@ -129,10 +129,13 @@ def test_sap_eo_single_block_is_global_eo_mr():
     assert rel(psi.ravel(), x) < 1e-12
 
 
-def test_fgmres_with_sap_eo_solves(setup):
-    dims, block, U, C, m0, M = setup
-    if block != (4, 4, 4, 4):
-        pytest.skip("one blocking is enough")
+def test_fgmres_with_sap_eo_solves():
+    # the 4^4 blocking of the setup fixture (one blocking is enough here)
+    dims, block = (4, 4, 4, 8), (4, 4, 4, 4)
+    U = synth.random_su3_links(dims, eps=0.4, seed=4)
+    C = oracle.clover_field(dims, U, 1.0)
+    m0 = -0.1
+    M = dirac_sparse(dims, U, C, m0, BC).tocsr()
     b = synth.gaussian_spinor(dims, seed=11)
     x, info = oracle.fgmres(dims, block, U, C, m0, b, m=10, tol=1e-10,
                             precond=lambda v: oracle.sap(dims, block, U, C, m0, v, 4, 4, BC, eo=True))
