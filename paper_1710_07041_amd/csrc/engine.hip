@@ -304,19 +304,21 @@ __device__ __forceinline__ LagCoef lag_coef(const double2 *row, int j)
 
 // Lagged pass (B) of step j: V[j] = v_j = (p_j - sum_{i<j} c_i V_i)/alpha
 // (j > 0), V[j+1] = p_{j+1} = (w - sum_{i<j} s_i V_i - h_jj v_j)/beta, and
-// lp = p_{j+1} in the smoother precision SL (lp == nullptr: none).  With
-// want_max, max|p_{j+1}| goes to partial slot K_MAX.  Inactive slots write
-// nothing.
+// lp = lsc * p_{j+1} in the smoother precision SL (lp == nullptr: none;
+// scl[r] = lsc when scl is given).  With want_max, max|p_{j+1}| goes to
+// partial slot K_MAX.  Inactive slots write nothing.
 template <int NV, typename SL>
 __global__ __launch_bounds__(TPB) void k_update_lag(double2 *__restrict__ V, long vstride,
                                                     const int *__restrict__ nv_dev, const double2 *__restrict__ res,
                                                     const double2 *__restrict__ w, vec2_t<SL> *__restrict__ lp,
+                                                    double lsc, double *__restrict__ scl,
                                                     double2 *__restrict__ partial, int want_max,
                                                     const int *__restrict__ active, int nblocks, int nrhs)
 {
     __shared__ double red[4];
     const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
     if (!active[r]) return;
+    if (scl && g == 0 && s == 0) scl[r] = lsc;
     const int j = nv_dev[r] - 1;
     const double2 *row = res + (long)r * KMAX;
     const LagCoef L = lag_coef(row, j);
@@ -346,32 +348,13 @@ __global__ __launch_bounds__(TPB) void k_update_lag(double2 *__restrict__ V, lon
             wc = wc - L.hjj * v;
             const C64 q = L.inv_beta * wc;
             stc_stream(pn + base + c * BS, q);
-            if (lp) stc(lp + base + c * BS, q);
+            if (lp) stc(lp + base + c * BS, lsc * q);
             mx = fmax(mx, fmax(fabs(q.re), fabs(q.im)));
         }
     }
     if (want_max) {
         const double tm = wg_max(mx, red);
         if (s == 0) partial[((long)g * nrhs + r) * KMAX + K_MAX] = make_double2(tm, 0.0);
-    }
-}
-
-// FP16 copy of the new basis vector: lp = scale_r * V[nv_r], scale_r =
-// 1/(1.0625 max|V[nv_r]|) (1 for a zero vector), stored in scl[r].
-__global__ __launch_bounds__(TPB) void k_to_half(const double2 *__restrict__ V, long vstride,
-                                                 const int *__restrict__ nv_dev, const double2 *__restrict__ mxred,
-                                                 __half2 *__restrict__ lp, double *__restrict__ scl,
-                                                 const int *__restrict__ active, int nblocks, int nrhs)
-{
-    const int g = blockIdx.x, G = gridDim.x, r = blockIdx.y, s = threadIdx.x;
-    if (!active[r]) return;
-    const double m = mxred[(long)r * KMAX + K_MAX].x * 1.0625;
-    const double sc = m > 0.0 ? 1.0 / m : 1.0;
-    if (g == 0 && s == 0) scl[r] = sc;
-    const double2 *src = V + nv_dev[r] * vstride;
-    for (int b = g; b < nblocks; b += G) {
-        const long base = ((long)b * nrhs + r) * 12 * BS + s;
-        for (int c = 0; c < 12; ++c) stc(lp + base + c * BS, sc * ldc_stream<double>(src + base + c * BS));
     }
 }
 
@@ -588,12 +571,13 @@ struct Engine::Impl {
         return Status::ok();
     }
     // lagged pass B: v_j over p_j, p_{j+1}, smoother-precision copy
-    template <typename SL> Status update_lag_t(int nb, void *lpp, bool want_max)
+    template <typename SL>
+    Status update_lag_t(int nb, void *lpp, bool want_max, double lsc = 1.0, double *sclp = nullptr)
     {
         ProfScope ps(ctx->prof, st(), K_CGS_UPDATE,
                      vec64() * (nb + 4) + (lpp ? (double)vlen * 2 * sizeof(SL) : 0.0), 16.0 * vlen * (nb + 1));
         switch (pick_bucket(nb)) {
-#define C(N) case N: k_update_lag<N, SL><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), res.as<double2>(), w.as<double2>(), static_cast<vec2_t<SL> *>(lpp), partial.as<double2>(), want_max ? 1 : 0, d_active(), ctx->g.nblocks, W); break;
+#define C(N) case N: k_update_lag<N, SL><<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), res.as<double2>(), w.as<double2>(), static_cast<vec2_t<SL> *>(lpp), lsc, sclp, partial.as<double2>(), want_max ? 1 : 0, d_active(), ctx->g.nblocks, W); break;
             DD_BUCKETS(C)
 #undef C
         }
@@ -604,14 +588,12 @@ struct Engine::Impl {
     {
         if (sap_prec == DD_F64) return update_lag_t<double>(nb, nullptr, false);
         if (sap_prec == DD_F32) return update_lag_t<float>(nb, lp.p, false);
-        // FP16: the scale needs max|p_{j+1}| first
-        DD_TRY(update_lag_t<float>(nb, nullptr, true));
-        DD_TRY(reduce(res2.as<double2>(), 0));
-        ProfScope ps(ctx->prof, st(), K_CONVERT, vec64() + (double)vlen * 4.0, 2.0 * vlen);
-        k_to_half<<<grid(), TPB, 0, st()>>>(V.as<double2>(), vlen, d_nv(), res2.as<double2>(), lp.as<__half2>(),
-                                            scl.as<double>(), d_active(), ctx->g.nblocks, W);
-        DD_HIP_TRY(hipGetLastError());
-        return Status::ok();
+        // FP16: p_{j+1} has unit 2-norm up to rounding (beta is its norm), so
+        // max|p_{j+1}| <= 1 and the fixed scale sqrt(24 V)/8 keeps the copy
+        // inside FP16's range (at most 4.1e4 for 2^32 sites) while its RMS
+        // entry, 1/8, sits far above the subnormals; the pass writes the
+        // copy itself
+        return update_lag_t<__half>(nb, lp.p, false, std::sqrt(24.0 * (double)ctx->g.V) / 8.0, scl.as<double>());
     }
     // nvmax == 0: plain |w|^2 and max|w| (no vectors, w untouched)
     Status update_dots(double2 *wv, int nvmax, const double2 *h)
